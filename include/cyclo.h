@@ -1,0 +1,139 @@
+/*
+ * cyclo.h - C ABI of the MI355X (gfx950) streaming cyclic-statistics library.
+ *
+ * A stream state accumulates, over every sample pushed into it, the cyclic
+ * autocorrelation and its conjugate form (the streaming estimator of Sec. 4,
+ * Eq. (11), applied to one signal x = y with non-negative lags; conjugate form
+ * as in Sec. 2, Eq. (9); normalised cycle frequencies as in Sec. 2):
+ *
+ *   N_used     = max(0, L - T + 1)   after L samples (one count for all lags)
+ *   R [t][a]   = (1/N_used) sum_{n<N_used} x[n+t] conj(x[n]) exp(-j2pi frac(alpha_a n))
+ *   Rc[t][a]   = (1/N_used) sum_{n<N_used} x[n+t]      x[n]  exp(-j2pi frac(alpha_a n))
+ *
+ * for lags t = 0..T-1 and a caller-given list of cycle frequencies alpha_a
+ * (cycles/sample, any real values; the tables are 1-periodic in alpha).  The
+ * sample index n is absolute: n = 0 is the first sample pushed after
+ * cyc_create() or cyc_reset(), so the phase carried across pushes plays the
+ * role of the `state` attribute of the paper's block (Sec. 4).  Any
+ * segmentation of the pushes gives bit-identical tables.
+ *
+ * Conventions for every call:
+ *  - Every function returns a status code (CYC_OK = 0, negative on error) and
+ *    never throws across the ABI.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    All device work of a call is enqueued on it asynchronously; calls on one
+ *    state must be ordered (same stream, or synchronised by the caller).
+ *  - Device pointers (d_*) are caller-owned; the library never frees them and
+ *    reads/writes them only from work enqueued on `stream`.
+ *  - A state is not thread-safe; distinct states are independent.
+ *  - After a device-side failure the state is poisoned: every call returns
+ *    CYC_ESTATE until cyc_reset().
+ */
+#ifndef CYCLO_H
+#define CYCLO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define CYC_OK            0
+#define CYC_EINVAL       -1  /* bad argument (NULL, negative size, non-finite alpha, ...) */
+#define CYC_ENOMEM       -2  /* device or host allocation failed */
+#define CYC_EDEVICE      -3  /* a HIP call or kernel launch failed; state poisoned */
+#define CYC_ESTATE       -4  /* state is poisoned; call cyc_reset() */
+#define CYC_EUNSUPPORTED -5  /* flag combination or size not supported */
+
+/* ---- flags for cyc_create ------------------------------------------------ */
+/* Operand precision of the matrix-core contraction (accumulation is always
+ * FP32 within a chunk and FP64 across chunks; the alpha*n reduction is FP64). */
+#define CYC_OP_FP32   0x0u   /* FP32 operands (default)                       */
+#define CYC_OP_BF16   0x1u   /* BF16 operands                                 */
+#define CYC_OP_FP16   0x2u   /* FP16 operands                                 */
+#define CYC_OP_MASK   0x3u
+/* Split the modulated operand conj(x[n])exp(-j2pi alpha n) (the one that holds
+ * the twiddle) into hi + lo parts of the operand precision: two matrix-core
+ * products per tile, about half the operand rounding error. BF16/FP16 only. */
+#define CYC_TW_SPLIT  0x4u
+/* cyc_read writes complex128 tables instead of complex64. */
+#define CYC_OUT_C128  0x8u
+
+typedef struct cyc_state cyc_state;
+
+/*
+ * Create a stream state.
+ *   out         : receives the new state (untouched on error).
+ *   alphas_host : host array of n_alpha FP64 cycle frequencies (copied).
+ *   n_alpha     : number of cycle frequencies, >= 1.
+ *   n_lag       : T, the number of lags 0..T-1, 1 <= T <= 4096.
+ *   flags       : CYC_OP_* | CYC_TW_SPLIT | CYC_OUT_C128.
+ *   stream      : stream for the set-up work; the call returns after it ends.
+ * Errors: CYC_EINVAL (NULL pointer, n_alpha < 1, n_lag out of range,
+ * non-finite alpha, unknown flag bits), CYC_EUNSUPPORTED (CYC_TW_SPLIT with
+ * FP32), CYC_ENOMEM, CYC_EDEVICE.
+ */
+int cyc_create(cyc_state** out, const double* alphas_host, int32_t n_alpha,
+               int32_t n_lag, uint32_t flags, void* stream);
+
+/*
+ * Push a block of n complex64 samples (interleaved re, im; 8-byte aligned,
+ * contiguous) that live in device memory at d_x.  Asynchronous: the caller
+ * must not overwrite d_x until `stream` has passed this call.  n = 0 is a
+ * no-op.  Errors: CYC_EINVAL (s NULL, n < 0, d_x NULL with n > 0),
+ * CYC_ESTATE, CYC_EDEVICE (poisons the state).
+ */
+int cyc_push(cyc_state* s, const void* d_x, int64_t n, void* stream);
+
+/*
+ * Read the current tables without changing the state.
+ *   d_R, d_Rc : caller-owned device buffers of T*n_alpha complex values,
+ *               row-major [t][a], complex64 (or complex128 with CYC_OUT_C128);
+ *               either may be NULL to skip that table.
+ *   n_used    : host pointer (may be NULL) that receives N_used.
+ * With N_used = 0 both tables are zero-filled and the call succeeds.
+ * Errors: CYC_EINVAL (s NULL), CYC_ESTATE, CYC_EDEVICE.
+ */
+int cyc_read(cyc_state* s, void* d_R, void* d_Rc, int64_t* n_used, void* stream);
+
+/*
+ * Forget every pushed sample and clear the poison flag; alphas, T and flags
+ * are kept.  Afterwards the state behaves exactly like a fresh one.  Host-only
+ * (enqueues no device work).  Errors: CYC_EINVAL (s NULL).
+ */
+int cyc_reset(cyc_state* s);
+
+/* Free the state and its device memory (synchronises the device). NULL is a no-op. */
+void cyc_destroy(cyc_state* s);
+
+/* Static, human-readable text for a status code. */
+const char* cyc_status_str(int code);
+
+/*
+ * Introspection (host-only): samples pushed, products committed to the FP64
+ * accumulator (a multiple of the chunk length), chunk length in samples, and
+ * the index of the contraction kernel configuration in use.  Any output
+ * pointer may be NULL.  Errors: CYC_EINVAL (s NULL).
+ */
+int cyc_query(const cyc_state* s, int64_t* n_pushed, int64_t* n_committed,
+              int32_t* chunk, int32_t* kernel_cfg);
+
+/*
+ * Kernel timing (tracing aid).  cyc_profile(s, 1) clears the counters and
+ * starts recording a pair of HIP events around every launch of the
+ * contraction kernel, on the stream that launch runs on; cyc_profile(s, 0)
+ * stops recording.  cyc_profile_read waits for the recorded events and
+ * returns the summed kernel time in milliseconds, the number of launches and
+ * the number of (alpha, tau, sample) triples those launches evaluated (each
+ * triple is one complex multiply-add per table).  Outputs may be NULL.
+ * Errors: CYC_EINVAL (s NULL), CYC_ENOMEM, CYC_EDEVICE.
+ */
+int cyc_profile(cyc_state* s, int32_t enable);
+int cyc_profile_read(cyc_state* s, double* total_ms, int64_t* launches, double* work);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CYCLO_H */

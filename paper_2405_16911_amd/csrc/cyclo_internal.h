@@ -1,0 +1,62 @@
+// Internal interfaces between the C-ABI runtime and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cyclo {
+
+// Virtual sample array: pend[0 .. n_pend) followed by xin[0 .. n_avail - n_pend).
+// Reads at or beyond n_avail return 0.
+struct VSrc {
+  const float2* pend;
+  const float2* xin;
+  int64_t n_pend;
+  int64_t n_avail;
+};
+
+// One launch of the chunk contraction: for chunk c (0 <= c < n_chunks) the
+// chunk-local partial sums
+//   part[c][0][t][a] = sum_{l < m_c} x[b_c+l+t] conj(x[b_c+l]) W[l][a]
+//   part[c][1][t][a] = sum_{l < m_c} x[b_c+l+t]      x[b_c+l]  W[l][a]
+// with b_c = v_off + c*Kc (virtual index), m_c = min(Kc, n_prod - c*Kc) and
+// the chunk-relative twiddle W[l][a] = H[a][l / KS] * Lo[a][l % KS]
+//                                  = exp(-j 2 pi frac(alpha_a l)).
+struct ContractArgs {
+  VSrc v;
+  int64_t v_off;
+  int64_t n_prod;
+  int T, A, Kc;
+  int n_tt, n_at, n_chunks;
+  const float2* H;   // [A][Kc/KS]
+  const float2* Lo;  // [A][KS]
+  float2* part;      // [n_chunks][2][T][A]
+};
+
+enum { PREC_F32 = 0, PREC_BF16 = 1, PREC_F16 = 2 };
+
+struct KernelCfg {
+  int prec;      // PREC_*
+  int split;     // modulated operand split into hi + lo
+  int tw;        // lags per workgroup tile
+  int aw;        // cycle frequencies per workgroup tile
+  int ks;        // samples per K step (twiddle table period)
+  int nthreads;  // workgroup size
+  hipError_t (*launch)(const ContractArgs&, int grid, hipStream_t);
+  const char* name;
+};
+
+const KernelCfg* kernel_cfgs(int* n);
+
+hipError_t launch_tables(const double* alpha_r, int A, int ks, int nsteps, float2* Lo,
+                         float2* H, hipStream_t st);
+hipError_t launch_phase(const double* alpha_r, int A, int64_t base0, int Kc, int nc,
+                        double2* E, hipStream_t st);
+hipError_t launch_accumulate(double2* S, const float2* part, const double2* E, int T, int A,
+                             int nc, int first, hipStream_t st);
+hipError_t launch_finalize(const double2* S, int hasS, const float2* part0, const double2* E0,
+                           int hasP, int T, int A, int64_t n_used, void* R, void* Rc, int c128,
+                           hipStream_t st);
+hipError_t launch_vcopy(VSrc v, int64_t shift, int64_t n, float2* dst, hipStream_t st);
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
+
+}  // namespace cyclo

@@ -1,0 +1,560 @@
+// gfx950 kernels of the streaming cyclic-statistics path.
+//
+// Contraction.  For one chunk of Kc products starting at sample b the tables
+// need, for lags t and cycle frequencies a,
+//   S [t][a] = sum_l x[b+l+t] conj(x[b+l]) E(a, b+l)
+//   Sc[t][a] = sum_l x[b+l+t]      x[b+l]  E(a, b+l)        (Sec. 4, Eq. (11))
+// and E(a, b+l) = E(a, b) * W[l][a] with W[l][a] = exp(-j2pi frac(alpha_a l)).
+// The chunk factor E(a, b) is applied later in FP64 (accumulate kernel).  The
+// chunk sum is a complex matrix product
+//   [S | Sc] = X (T x K) . [Y | Yc] (K x 2A)
+// with the Hankel operand X[t][l] = x[b+l+t] (the sample window and its
+// lag-shifted copies, staged in LDS without any arithmetic) and the modulated
+// operands Y[l][a] = conj(x[b+l]) W[l][a], Yc[l][a] = x[b+l] W[l][a]; the lag
+// products x[n+t]x*[n] are formed inside the matrix cores.  Written as one real
+// GEMM with the complex parts interleaved along K (k = 2l + c):
+//   A'[(t,0)][(l,0)] =  Re x[b+l+t]   A'[(t,0)][(l,1)] = -Im x[b+l+t]
+//   A'[(t,1)][(l,0)] =  Im x[b+l+t]   A'[(t,1)][(l,1)] =  Re x[b+l+t]
+//   B'[(l,c)][q]     =  component c of Y (q < A) or Yc (q >= A)
+// so C'[(t,0)][q] = Re, C'[(t,1)][q] = Im of the table entry, with exactly
+// 8 real flops per complex multiply-add and no wasted products.
+//
+// Twiddles.  W[l][a] = H[a][l / KS] * Lo[a][l % KS] (one complex multiply per
+// element) from per-alpha tables made once per state in FP64 (error-free
+// alpha*n reduction, FP64 sincospi) and stored in FP32.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cyclo_internal.h"
+
+namespace cyclo {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// ----------------------------------------------------------------------------- helpers
+
+__device__ __forceinline__ float2 vload(const VSrc& v, int64_t g) {
+  if (g < v.n_pend) return v.pend[g];
+  if (g < v.n_avail) return v.xin[g - v.n_pend];
+  return make_float2(0.f, 0.f);
+}
+
+__device__ __forceinline__ float2 cmul(float2 p, float2 q) {
+  return make_float2(p.x * q.x - p.y * q.y, p.x * q.y + p.y * q.x);
+}
+
+// frac(alpha * n) in [0, 1): error-free product p + e = alpha*n (FMA), then
+// (p - floor(p)) + e, wrapped.  |alpha| <= 1/2 and |n| < 2^53.
+__device__ __forceinline__ double frac_prod(double alpha, int64_t n) {
+  const double nd = (double)n;
+  const double p = alpha * nd;
+  const double e = __fma_rn(alpha, nd, -p);
+  double phi = (p - floor(p)) + e;
+  phi -= floor(phi);
+  return phi >= 1.0 ? 0.0 : phi;
+}
+
+template <int PREC>
+struct Op;
+
+template <>
+struct Op<PREC_BF16> {
+  typedef __bf16 e2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 e8 __attribute__((ext_vector_type(8)));
+  static __device__ __forceinline__ uint32_t pack(float a, float b) {
+    e2 v;
+    v.x = (__bf16)a;
+    v.y = (__bf16)b;
+    return __builtin_bit_cast(uint32_t, v);
+  }
+  static __device__ __forceinline__ float rnd(float a) { return (float)(__bf16)a; }
+  static __device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(e8, a),
+                                                  __builtin_bit_cast(e8, b), c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Op<PREC_F16> {
+  typedef _Float16 e2 __attribute__((ext_vector_type(2)));
+  typedef _Float16 e8 __attribute__((ext_vector_type(8)));
+  static __device__ __forceinline__ uint32_t pack(float a, float b) {
+    e2 v;
+    v.x = (_Float16)a;
+    v.y = (_Float16)b;
+    return __builtin_bit_cast(uint32_t, v);
+  }
+  static __device__ __forceinline__ float rnd(float a) { return (float)(_Float16)a; }
+  static __device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(e8, a),
+                                                 __builtin_bit_cast(e8, b), c, 0, 0, 0);
+  }
+};
+
+// Block index -> (chunk, lag tile, alpha tile).
+struct TileId {
+  int chunk, tt, at;
+};
+__device__ __forceinline__ TileId tile_of(const ContractArgs& a) {
+  int bid = blockIdx.x;
+  TileId r;
+  r.at = bid % a.n_at;
+  bid /= a.n_at;
+  r.tt = bid % a.n_tt;
+  r.chunk = bid / a.n_tt;
+  return r;
+}
+
+// Stores one wave's 32x32 accumulator blocks: rows (t, re/im) interleaved,
+// columns q < AW -> table 0 (R), q >= AW -> table 1 (Rc).
+template <int WM, int WN, int AW>
+__device__ __forceinline__ void store_tiles(const ContractArgs& a, const TileId& id, int tau0,
+                                            int alpha0, int wm, int wn, int lane,
+                                            const f32x16 (&acc)[WM][WN]) {
+  const int h = lane >> 5, l32 = lane & 31;
+  const int64_t TA = (int64_t)a.T * a.A;
+  float2* base = a.part + (int64_t)id.chunk * 2 * TA;
+#pragma unroll
+  for (int cb = 0; cb < WN; ++cb) {
+    const int q = (wn * WN + cb) * 32 + l32;
+    const int table = q >= AW ? 1 : 0;
+    const int alpha = alpha0 + (q - table * AW);
+    if (alpha >= a.A) continue;
+    float2* tb = base + table * TA + alpha;
+#pragma unroll
+    for (int rb = 0; rb < WM; ++rb) {
+#pragma unroll
+      for (int v = 0; v < 16; v += 2) {
+        const int row = 8 * (v >> 2) + 4 * h + (v & 3);
+        const int R = (wm * WM + rb) * 32 + row;
+        const int tau = tau0 + (R >> 1);
+        if (tau < a.T) tb[(int64_t)tau * a.A] = make_float2(acc[rb][cb][v], acc[rb][cb][v + 1]);
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------- FP32 contraction
+//
+// v_mfma_f32_32x32x2f32: one complex sample per instruction (K' = 2 = re, im).
+// A lane holds A'[row = lane%32][k = lane/32] and B'[k = lane/32][col = lane%32].
+template <int TW, int AW, int WAVES_M, int WAVES_N, int KS>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_f32(ContractArgs a) {
+  constexpr int NT = 64 * WAVES_M * WAVES_N;
+  constexpr int MR = 2 * TW, NC = 2 * AW;
+  constexpr int WM = MR / (32 * WAVES_M), WN = NC / (32 * WAVES_N);
+  static_assert(WM * 32 * WAVES_M == MR && WN * 32 * WAVES_N == NC, "tile");
+  constexpr int G = KS * AW / NT;
+  static_assert(G >= 1 && G * NT == KS * AW && KS % G == 0, "B-gen split");
+  constexpr int XP = TW + KS;  // staged samples per step
+
+  __shared__ __attribute__((aligned(16))) float4 Xs[2][XP];     // (re, -im, im, re)
+  __shared__ __attribute__((aligned(16))) float2 Bs[2][KS][NC];  // [j][q] = (re, im)
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WAVES_M, wn = wave / WAVES_M;
+  const int h = lane >> 5, l32 = lane & 31;
+  const TileId id = tile_of(a);
+  const int tau0 = id.tt * TW, alpha0 = id.at * AW;
+  const int64_t cbase = a.v_off + (int64_t)id.chunk * a.Kc;
+  const int64_t mprod = min((int64_t)a.Kc, a.n_prod - (int64_t)id.chunk * a.Kc);
+  const int nsteps = a.Kc / KS;
+  const int nsteps_eff = (int)((mprod + KS - 1) / KS);
+
+  // modulated-operand generator role: one alpha, G consecutive samples
+  const int ga = tid % AW, gj = (tid / AW) * G;
+  const int galpha = alpha0 + ga;
+  const bool aval = galpha < a.A;
+  float2 lo[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+    lo[g] = aval ? a.Lo[(int64_t)galpha * KS + gj + g] : make_float2(0.f, 0.f);
+  const float2* Hrow = a.H + (int64_t)(aval ? galpha : 0) * nsteps;
+
+  auto produce = [&](int ks, int buf) {
+    const int64_t s0 = cbase + (int64_t)ks * KS;
+    for (int p = tid; p < XP; p += NT) {
+      const float2 v = vload(a.v, s0 + tau0 + p);
+      Xs[buf][p] = make_float4(v.x, -v.y, v.y, v.x);
+    }
+    const float2 hv = aval ? Hrow[ks] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int j = gj + g;
+      const bool valid = aval && ((int64_t)ks * KS + j < mprod);
+      const float2 xv = vload(a.v, s0 + j);
+      const float2 w = cmul(hv, lo[g]);
+      float2 y = make_float2(xv.x * w.x + xv.y * w.y, xv.x * w.y - xv.y * w.x);
+      float2 yc = make_float2(xv.x * w.x - xv.y * w.y, xv.x * w.y + xv.y * w.x);
+      if (!valid) y = yc = make_float2(0.f, 0.f);
+      Bs[buf][j][ga] = y;
+      Bs[buf][j][AW + ga] = yc;
+    }
+  };
+
+  f32x16 acc[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int k = 0; k < WN; ++k)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][k][v] = 0.f;
+
+  if (nsteps_eff > 0) produce(0, 0);
+  __syncthreads();
+  for (int ks = 0; ks < nsteps_eff; ++ks) {
+    const int buf = ks & 1;
+#pragma unroll 4
+    for (int j = 0; j < KS; ++j) {
+      float af[WM], bf[WN];
+#pragma unroll
+      for (int rb = 0; rb < WM; ++rb) {
+        const int R = (wm * WM + rb) * 32 + l32;
+        af[rb] = reinterpret_cast<const float*>(&Xs[buf][0])[4 * (j + (R >> 1)) + 2 * (R & 1) + h];
+      }
+#pragma unroll
+      for (int cb = 0; cb < WN; ++cb) {
+        bf[cb] = reinterpret_cast<const float*>(&Bs[buf][j][0])[2 * ((wn * WN + cb) * 32 + l32) + h];
+      }
+#pragma unroll
+      for (int rb = 0; rb < WM; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < WN; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[rb], bf[cb], acc[rb][cb], 0, 0, 0);
+    }
+    if (ks + 1 < nsteps_eff) produce(ks + 1, buf ^ 1);
+    __syncthreads();
+  }
+  store_tiles<WM, WN, AW>(a, id, tau0, alpha0, wm, wn, lane, acc);
+}
+
+// ----------------------------------------------------------------------------- BF16/FP16 contraction
+//
+// v_mfma_f32_32x32x16_{bf16,f16}: a lane holds A'[row = lane%32][8*(lane/32) + s]
+// and B'[8*(lane/32) + s][col = lane%32], s = 0..7, i.e. four consecutive complex
+// samples (re, im interleaved) starting at sample 4*(lane/32) of the 8-sample
+// K block.  The Hankel operand is staged as four copies shifted by 0..3 samples
+// so every 16-byte fragment read is aligned whatever the lag.
+template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_16(ContractArgs a) {
+  using O = Op<PREC>;
+  constexpr int NT = 64 * WAVES_M * WAVES_N;
+  constexpr int MR = 2 * TW, NC = 2 * AW;
+  constexpr int WM = MR / (32 * WAVES_M), WN = NC / (32 * WAVES_N);
+  static_assert(WM * 32 * WAVES_M == MR && WN * 32 * WAVES_N == NC, "tile");
+  static_assert(KS % 8 == 0 && TW % 16 == 0, "shape");
+  constexpr int G = KS * AW / NT;
+  static_assert(G >= 4 && G * NT == KS * AW && KS % G == 0 && G % 4 == 0, "B-gen split");
+  constexpr int ZW = KS + TW;          // entries per shifted copy (multiple of 4)
+  constexpr int ZU = 2 * 4 * (ZW / 4); // staging units of 4 entries
+  constexpr int BP = KS + 4;           // B row pitch (uint32), keeps rows 16-byte aligned
+  constexpr int NB = SPLIT ? 2 : 1;
+
+  __shared__ __attribute__((aligned(16))) uint32_t Zs[2][2][4][ZW];
+  __shared__ __attribute__((aligned(16))) uint32_t Bs[2][NB][NC][BP];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WAVES_M, wn = wave / WAVES_M;
+  const int h = lane >> 5, l32 = lane & 31;
+  const TileId id = tile_of(a);
+  const int tau0 = id.tt * TW, alpha0 = id.at * AW;
+  const int64_t cbase = a.v_off + (int64_t)id.chunk * a.Kc;
+  const int64_t mprod = min((int64_t)a.Kc, a.n_prod - (int64_t)id.chunk * a.Kc);
+  const int nsteps = a.Kc / KS;
+  const int nsteps_eff = (int)((mprod + KS - 1) / KS);
+
+  const int ga = tid % AW, gj = (tid / AW) * G;
+  const int galpha = alpha0 + ga;
+  const bool aval = galpha < a.A;
+  float2 lo[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+    lo[g] = aval ? a.Lo[(int64_t)galpha * KS + gj + g] : make_float2(0.f, 0.f);
+  const float2* Hrow = a.H + (int64_t)(aval ? galpha : 0) * nsteps;
+
+  auto produce = [&](int ks, int buf) {
+    const int64_t s0 = cbase + (int64_t)ks * KS;
+    // Hankel operand: copy (cr, sh) entry i holds the pair for sample s0+tau0+i+sh,
+    // cr = 0: (re, -im), cr = 1: (im, re).
+    for (int u = tid; u < ZU; u += NT) {
+      const int grp = u % (ZW / 4);
+      const int sh = (u / (ZW / 4)) & 3;
+      const int cr = u / ZW;
+      const int64_t g0 = s0 + tau0 + 4 * grp + sh;
+      uint32_t w[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float2 v = vload(a.v, g0 + k);
+        w[k] = cr ? O::pack(v.y, v.x) : O::pack(v.x, -v.y);
+      }
+      *reinterpret_cast<uint4*>(&Zs[buf][cr][sh][4 * grp]) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    // Modulated operands.
+    const float2 hv = aval ? Hrow[ks] : make_float2(0.f, 0.f);
+    uint32_t py[NB][G], pyc[NB][G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int j = gj + g;
+      const bool valid = aval && ((int64_t)ks * KS + j < mprod);
+      const float2 xv = vload(a.v, s0 + j);
+      const float2 w = cmul(hv, lo[g]);
+      float2 y = make_float2(xv.x * w.x + xv.y * w.y, xv.x * w.y - xv.y * w.x);
+      float2 yc = make_float2(xv.x * w.x - xv.y * w.y, xv.x * w.y + xv.y * w.x);
+      if (!valid) y = yc = make_float2(0.f, 0.f);
+      py[0][g] = O::pack(y.x, y.y);
+      pyc[0][g] = O::pack(yc.x, yc.y);
+      if (SPLIT) {
+        py[NB - 1][g] = O::pack(y.x - O::rnd(y.x), y.y - O::rnd(y.y));
+        pyc[NB - 1][g] = O::pack(yc.x - O::rnd(yc.x), yc.y - O::rnd(yc.y));
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int g = 0; g < G; g += 4) {
+        *reinterpret_cast<uint4*>(&Bs[buf][b][ga][gj + g]) =
+            make_uint4(py[b][g], py[b][g + 1], py[b][g + 2], py[b][g + 3]);
+        *reinterpret_cast<uint4*>(&Bs[buf][b][AW + ga][gj + g]) =
+            make_uint4(pyc[b][g], pyc[b][g + 1], pyc[b][g + 2], pyc[b][g + 3]);
+      }
+  };
+
+  f32x16 acc[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int k = 0; k < WN; ++k)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][k][v] = 0.f;
+
+  // per-lane Hankel read offsets (fixed for the whole kernel)
+  int zoff[WM], zcr[WM], zsh[WM];
+#pragma unroll
+  for (int rb = 0; rb < WM; ++rb) {
+    const int R = (wm * WM + rb) * 32 + l32;
+    const int p0 = (R >> 1) + 4 * h;
+    zcr[rb] = R & 1;
+    zsh[rb] = p0 & 3;
+    zoff[rb] = p0 - zsh[rb];
+  }
+
+  if (nsteps_eff > 0) produce(0, 0);
+  __syncthreads();
+  for (int ks = 0; ks < nsteps_eff; ++ks) {
+    const int buf = ks & 1;
+#pragma unroll
+    for (int kb = 0; kb < KS / 8; ++kb) {
+      const int j0 = kb * 8;
+      uint4 af[WM], bf[NB][WN];
+#pragma unroll
+      for (int rb = 0; rb < WM; ++rb)
+        af[rb] = *reinterpret_cast<const uint4*>(&Zs[buf][zcr[rb]][zsh[rb]][zoff[rb] + j0]);
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int cb = 0; cb < WN; ++cb)
+          bf[b][cb] = *reinterpret_cast<const uint4*>(
+              &Bs[buf][b][(wn * WN + cb) * 32 + l32][j0 + 4 * h]);
+#pragma unroll
+      for (int rb = 0; rb < WM; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < WN; ++cb) {
+          acc[rb][cb] = O::mfma(af[rb], bf[0][cb], acc[rb][cb]);
+          if (SPLIT) acc[rb][cb] = O::mfma(af[rb], bf[NB - 1][cb], acc[rb][cb]);
+        }
+    }
+    if (ks + 1 < nsteps_eff) produce(ks + 1, buf ^ 1);
+    __syncthreads();
+  }
+  store_tiles<WM, WN, AW>(a, id, tau0, alpha0, wm, wn, lane, acc);
+}
+
+// ----------------------------------------------------------------------------- config table
+
+template <int TW, int AW, int WAVES_M, int WAVES_N, int KS>
+hipError_t launch_f32(const ContractArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((contract_f32<TW, AW, WAVES_M, WAVES_N, KS>), dim3(grid),
+                     dim3(64 * WAVES_M * WAVES_N), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS>
+hipError_t launch_16(const ContractArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((contract_16<PREC, SPLIT, TW, AW, WAVES_M, WAVES_N, KS>), dim3(grid),
+                     dim3(64 * WAVES_M * WAVES_N), 0, st, a);
+  return hipGetLastError();
+}
+
+#define CFG_F32(TW, AW, WMW, WNW, KS)                                                       \
+  {PREC_F32, 0, TW, AW, KS, 64 * WMW * WNW, &launch_f32<TW, AW, WMW, WNW, KS>,              \
+   "f32_t" #TW "_a" #AW "_w" #WMW "x" #WNW "_k" #KS}
+#define CFG_16(P, PN, SP, TW, AW, WMW, WNW, KS)                                             \
+  {P, SP, TW, AW, KS, 64 * WMW * WNW, &launch_16<P, SP, TW, AW, WMW, WNW, KS>,              \
+   PN "_s" #SP "_t" #TW "_a" #AW "_w" #WMW "x" #WNW "_k" #KS}
+#define CFG_16_ALL(TW, AW, WMW, WNW, KS)                \
+  CFG_16(PREC_BF16, "bf16", 0, TW, AW, WMW, WNW, KS),   \
+  CFG_16(PREC_BF16, "bf16", 1, TW, AW, WMW, WNW, KS),   \
+  CFG_16(PREC_F16, "f16", 0, TW, AW, WMW, WNW, KS),     \
+  CFG_16(PREC_F16, "f16", 1, TW, AW, WMW, WNW, KS)
+
+static const KernelCfg g_cfgs[] = {
+    CFG_F32(128, 64, 4, 1, 16),
+    CFG_F32(64, 64, 2, 1, 16),
+    CFG_F32(32, 64, 1, 2, 16),
+    CFG_F32(64, 128, 2, 2, 16),
+    CFG_16_ALL(128, 64, 4, 1, 32),
+    CFG_16_ALL(64, 64, 2, 1, 32),
+    CFG_16_ALL(32, 64, 1, 2, 32),
+    CFG_16_ALL(64, 128, 2, 2, 32),
+};
+
+const KernelCfg* kernel_cfgs(int* n) {
+  *n = (int)(sizeof(g_cfgs) / sizeof(g_cfgs[0]));
+  return g_cfgs;
+}
+
+// ----------------------------------------------------------------------------- small kernels
+
+// Lo[a][k] = exp(-j2pi frac(alpha_a k)), k < ks;  H[a][s] = exp(-j2pi frac(alpha_a s ks)).
+__global__ void tables_kernel(const double* alpha_r, int A, int ks, int nsteps, float2* Lo,
+                              float2* H) {
+  const int64_t per = ks + nsteps;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)A * per) return;
+  const int a = (int)(i / per), k = (int)(i % per);
+  const int64_t n = k < ks ? (int64_t)k : (int64_t)(k - ks) * ks;
+  double s, c;
+  sincospi(2.0 * frac_prod(alpha_r[a], n), &s, &c);
+  const float2 w = make_float2((float)c, (float)-s);
+  if (k < ks)
+    Lo[(int64_t)a * ks + k] = w;
+  else
+    H[(int64_t)a * nsteps + (k - ks)] = w;
+}
+
+// E[c][a] = exp(-j2pi frac(alpha_a (base0 + c Kc))) in FP64 (absolute sample index).
+__global__ void phase_kernel(const double* alpha_r, int A, int64_t base0, int Kc, int nc,
+                             double2* E) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nc * A) return;
+  const int c = (int)(i / A), a = (int)(i % A);
+  double s, co;
+  sincospi(2.0 * frac_prod(alpha_r[a], base0 + (int64_t)c * Kc), &s, &co);
+  E[i] = make_double2(co, -s);
+}
+
+// S += sum_c part[c] * E[c] in FP64, chunks in ascending order (first: S starts at 0).
+__global__ void accumulate_kernel(double2* S, const float2* part, const double2* E, int T, int A,
+                                  int nc, int first) {
+  const int64_t n2 = 2 * (int64_t)T * A;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n2) return;
+  const int a = (int)(i % A);
+  double2 s = first ? make_double2(0.0, 0.0) : S[i];
+  for (int c = 0; c < nc; ++c) {
+    const float2 p = part[(int64_t)c * n2 + i];
+    const double2 e = E[(int64_t)c * A + a];
+    const double pr = p.x, pi = p.y;
+    s.x += pr * e.x - pi * e.y;
+    s.y += pr * e.y + pi * e.x;
+  }
+  S[i] = s;
+}
+
+// out[t][a] = (S + part0 * E0) / n_used for both tables.
+template <int C128>
+__global__ void finalize_kernel(const double2* S, int hasS, const float2* part0, const double2* E0,
+                                int hasP, int T, int A, double nd, void* R, void* Rc) {
+  const int64_t TA = (int64_t)T * A;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * TA) return;
+  const int table = i >= TA ? 1 : 0;
+  void* out = table ? Rc : R;
+  if (out == nullptr) return;
+  const int64_t r = i - table * TA;
+  const int a = (int)(r % A);
+  double sr = 0.0, si = 0.0;
+  if (hasS) {
+    const double2 s = S[i];
+    sr = s.x;
+    si = s.y;
+  }
+  if (hasP) {
+    const float2 p = part0[i];
+    const double2 e = E0[a];
+    const double pr = p.x, pi = p.y;
+    sr += pr * e.x - pi * e.y;
+    si += pr * e.y + pi * e.x;
+  }
+  sr /= nd;
+  si /= nd;
+  if (C128)
+    reinterpret_cast<double2*>(out)[r] = make_double2(sr, si);
+  else
+    reinterpret_cast<float2*>(out)[r] = make_float2((float)sr, (float)si);
+}
+
+__global__ void vcopy_kernel(VSrc v, int64_t shift, int64_t n, float2* dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = vload(v, shift + i);
+}
+
+__global__ void zero_kernel(uint32_t* p, int64_t nwords) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nwords) p[i] = 0u;
+}
+
+static inline int nblocks(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
+
+hipError_t launch_tables(const double* alpha_r, int A, int ks, int nsteps, float2* Lo, float2* H,
+                         hipStream_t st) {
+  const int64_t n = (int64_t)A * (ks + nsteps);
+  hipLaunchKernelGGL(tables_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, alpha_r, A, ks,
+                     nsteps, Lo, H);
+  return hipGetLastError();
+}
+
+hipError_t launch_phase(const double* alpha_r, int A, int64_t base0, int Kc, int nc, double2* E,
+                        hipStream_t st) {
+  const int64_t n = (int64_t)A * nc;
+  hipLaunchKernelGGL(phase_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, alpha_r, A, base0, Kc,
+                     nc, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_accumulate(double2* S, const float2* part, const double2* E, int T, int A, int nc,
+                             int first, hipStream_t st) {
+  const int64_t n = 2 * (int64_t)T * A;
+  hipLaunchKernelGGL(accumulate_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, S, part, E, T, A,
+                     nc, first);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double2* S, int hasS, const float2* part0, const double2* E0,
+                           int hasP, int T, int A, int64_t n_used, void* R, void* Rc, int c128,
+                           hipStream_t st) {
+  const int64_t n = 2 * (int64_t)T * A;
+  if (c128)
+    hipLaunchKernelGGL(finalize_kernel<1>, dim3(nblocks(n, 256)), dim3(256), 0, st, S, hasS, part0,
+                       E0, hasP, T, A, (double)n_used, R, Rc);
+  else
+    hipLaunchKernelGGL(finalize_kernel<0>, dim3(nblocks(n, 256)), dim3(256), 0, st, S, hasS, part0,
+                       E0, hasP, T, A, (double)n_used, R, Rc);
+  return hipGetLastError();
+}
+
+hipError_t launch_vcopy(VSrc v, int64_t shift, int64_t n, float2* dst, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(vcopy_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, v, shift, n, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st) {
+  const int64_t nw = bytes / 4;
+  if (nw <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_kernel, dim3(nblocks(nw, 256)), dim3(256), 0, st,
+                     reinterpret_cast<uint32_t*>(p), nw);
+  return hipGetLastError();
+}
+
+}  // namespace cyclo

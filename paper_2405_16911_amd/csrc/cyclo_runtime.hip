@@ -1,0 +1,358 @@
+// Stream state and C ABI (include/cyclo.h) of the cyclic-statistics library.
+//
+// State layout in HBM (one stream):
+//   alpha_r [A]            FP64 cycle frequencies reduced to [-1/2, 1/2]
+//   Lo [A][KS], H [A][Kc/KS]  FP32 chunk-relative twiddle tables
+//   S [2][T][A]            FP64 complex accumulators (R, Rc) over committed chunks
+//   pend[2][Kc+T-1]        ping-pong buffers of not-yet-committed samples
+//   part [maxc][2][T][A]   FP32 complex chunk partials (workspace)
+//   E [maxc][A]            FP64 complex per-chunk phase factors (workspace)
+//
+// Products are committed in chunks aligned to absolute indices [c Kc, (c+1) Kc)
+// as soon as their samples are all present, in ascending c, so the committed
+// accumulator after L samples does not depend on how the samples were pushed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/cyclo.h"
+#include "cyclo_internal.h"
+
+using namespace cyclo;
+
+struct cyc_state {
+  int T = 0, A = 0;
+  uint32_t flags = 0;
+  int Kc = 0, KS = 0, nsteps = 0;
+  int cfg = -1;
+  int maxc = 0;
+  double* alpha_r = nullptr;
+  float2* Lo = nullptr;
+  float2* H = nullptr;
+  double2* S = nullptr;
+  float2* pend[2] = {nullptr, nullptr};
+  int cur = 0;
+  float2* part = nullptr;
+  double2* E = nullptr;
+  int64_t L = 0;
+  int64_t nc = 0;  // products committed
+  bool poisoned = false;
+  // contraction-kernel timing
+  bool prof = false;
+  std::vector<hipEvent_t> ev;  // start/end pairs
+  size_t ev_used = 0;
+  double prof_work = 0.0;
+};
+
+namespace {
+
+constexpr int kMaxLag = 4096;
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int64_t env_i64(const char* name, int64_t dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  char* end = nullptr;
+  long long r = std::strtoll(v, &end, 10);
+  return (end && *end == 0) ? (int64_t)r : dflt;
+}
+
+// Chooses the contraction kernel for (precision, split, T, A).  CYC_KERNEL_CFG
+// overrides with an index into the configuration table when it matches.
+int pick_cfg(int prec, int split, int T) {
+  int n = 0;
+  const KernelCfg* c = kernel_cfgs(&n);
+  const int64_t forced = env_i64("CYC_KERNEL_CFG", -1);
+  if (forced >= 0 && forced < n && c[forced].prec == prec && c[forced].split == split)
+    return (int)forced;
+  const int want_tw = T > 64 ? 128 : (T > 32 ? 64 : 32);
+  for (int i = 0; i < n; ++i)
+    if (c[i].prec == prec && c[i].split == split && c[i].tw == want_tw && c[i].aw == 64) return i;
+  return -1;
+}
+
+void free_state(cyc_state* s) {
+  if (!s) return;
+  for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+  (void)hipFree(s->alpha_r);
+  (void)hipFree(s->Lo);
+  (void)hipFree(s->H);
+  (void)hipFree(s->S);
+  (void)hipFree(s->pend[0]);
+  (void)hipFree(s->pend[1]);
+  (void)hipFree(s->part);
+  (void)hipFree(s->E);
+  delete s;
+}
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  return hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T));
+}
+
+int fail_device(cyc_state* s) {
+  s->poisoned = true;
+  return CYC_EDEVICE;
+}
+
+}  // namespace
+
+static hipError_t run_contract(cyc_state* s, const VSrc& v, int64_t v_off, int64_t n_prod, int nch,
+                               hipStream_t st) {
+  int ncfg = 0;
+  const KernelCfg& cfg = kernel_cfgs(&ncfg)[s->cfg];
+  ContractArgs a;
+  a.v = v;
+  a.v_off = v_off;
+  a.n_prod = n_prod;
+  a.T = s->T;
+  a.A = s->A;
+  a.Kc = s->Kc;
+  a.n_tt = (s->T + cfg.tw - 1) / cfg.tw;
+  a.n_at = (s->A + cfg.aw - 1) / cfg.aw;
+  a.n_chunks = nch;
+  a.H = s->H;
+  a.Lo = s->Lo;
+  a.part = s->part;
+  const int64_t grid = (int64_t)a.n_tt * a.n_at * nch;
+  if (grid <= 0 || grid > 0x7fffffff) return hipErrorInvalidValue;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (s->prof) {
+    while (s->ev.size() < s->ev_used + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return hipErrorOutOfMemory;
+      s->ev.push_back(e);
+    }
+    e0 = s->ev[s->ev_used];
+    e1 = s->ev[s->ev_used + 1];
+    s->ev_used += 2;
+    s->prof_work += (double)n_prod * s->T * s->A;
+    hipError_t r = hipEventRecord(e0, st);
+    if (r != hipSuccess) return r;
+  }
+  hipError_t r = cfg.launch(a, (int)grid, st);
+  if (r == hipSuccess && e1) r = hipEventRecord(e1, st);
+  return r;
+}
+
+extern "C" {
+
+const char* cyc_status_str(int code) {
+  switch (code) {
+    case CYC_OK: return "ok";
+    case CYC_EINVAL: return "invalid argument";
+    case CYC_ENOMEM: return "out of memory";
+    case CYC_EDEVICE: return "device error (state poisoned)";
+    case CYC_ESTATE: return "state poisoned by an earlier device error; call cyc_reset";
+    case CYC_EUNSUPPORTED: return "unsupported flag combination or size";
+    default: return "unknown status code";
+  }
+}
+
+int cyc_create(cyc_state** out, const double* alphas_host, int32_t n_alpha, int32_t n_lag,
+               uint32_t flags, void* stream) {
+  if (!out || !alphas_host || n_alpha < 1 || n_lag < 1 || n_lag > kMaxLag) return CYC_EINVAL;
+  if (flags & ~(CYC_OP_MASK | CYC_TW_SPLIT | CYC_OUT_C128)) return CYC_EINVAL;
+  const int prec = (int)(flags & CYC_OP_MASK);
+  if (prec == 3) return CYC_EINVAL;
+  const int split = (flags & CYC_TW_SPLIT) ? 1 : 0;
+  if (split && prec == PREC_F32) return CYC_EUNSUPPORTED;
+  for (int32_t i = 0; i < n_alpha; ++i)
+    if (!std::isfinite(alphas_host[i])) return CYC_EINVAL;
+
+  cyc_state* s = new (std::nothrow) cyc_state();
+  if (!s) return CYC_ENOMEM;
+  s->T = n_lag;
+  s->A = n_alpha;
+  s->flags = flags;
+  s->cfg = pick_cfg(prec, split, n_lag);
+  if (s->cfg < 0) {
+    delete s;
+    return CYC_EUNSUPPORTED;
+  }
+  int ncfg = 0;
+  const KernelCfg& cfg = kernel_cfgs(&ncfg)[s->cfg];
+  s->KS = cfg.ks;
+  int64_t kc = env_i64("CYC_CHUNK", 4096);
+  kc = std::max<int64_t>(cfg.ks, std::min<int64_t>(kc, 1 << 20));
+  kc = (kc / cfg.ks) * cfg.ks;
+  s->Kc = (int)kc;
+  s->nsteps = s->Kc / s->KS;
+
+  const int64_t TA2 = 2 * (int64_t)s->T * s->A;
+  const int64_t ws_bytes = env_i64("CYC_WORKSPACE_MB", 256) << 20;
+  s->maxc = (int)std::max<int64_t>(1, std::min<int64_t>(4096, ws_bytes / (TA2 * 8)));
+
+  hipStream_t st = as_stream(stream);
+  // alpha reduced to [-1/2, 1/2]: the tables are 1-periodic in alpha and the
+  // reduction alpha - rint(alpha) is exact in FP64.
+  double* ar = new (std::nothrow) double[n_alpha];
+  if (!ar) {
+    delete s;
+    return CYC_ENOMEM;
+  }
+  for (int32_t i = 0; i < n_alpha; ++i) ar[i] = alphas_host[i] - std::nearbyint(alphas_host[i]);
+
+  int rc = CYC_OK;
+  if (dalloc(&s->alpha_r, s->A) != hipSuccess || dalloc(&s->Lo, (size_t)s->A * s->KS) != hipSuccess ||
+      dalloc(&s->H, (size_t)s->A * s->nsteps) != hipSuccess || dalloc(&s->S, (size_t)TA2) != hipSuccess ||
+      dalloc(&s->pend[0], (size_t)s->Kc + s->T) != hipSuccess ||
+      dalloc(&s->pend[1], (size_t)s->Kc + s->T) != hipSuccess ||
+      dalloc(&s->part, (size_t)s->maxc * TA2) != hipSuccess ||
+      dalloc(&s->E, (size_t)s->maxc * s->A) != hipSuccess) {
+    rc = CYC_ENOMEM;
+  }
+  if (rc == CYC_OK) {
+    if (hipMemcpyAsync(s->alpha_r, ar, sizeof(double) * s->A, hipMemcpyHostToDevice, st) != hipSuccess ||
+        launch_tables(s->alpha_r, s->A, s->KS, s->nsteps, s->Lo, s->H, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      rc = CYC_EDEVICE;
+  }
+  delete[] ar;
+  if (rc != CYC_OK) {
+    (void)hipGetLastError();
+    free_state(s);
+    return rc;
+  }
+  *out = s;
+  return CYC_OK;
+}
+
+int cyc_push(cyc_state* s, const void* d_x, int64_t n, void* stream) {
+  if (!s || n < 0 || (n > 0 && !d_x)) return CYC_EINVAL;
+  if (s->poisoned) return CYC_ESTATE;
+  if (n == 0) return CYC_OK;
+  hipStream_t st = as_stream(stream);
+  const float2* x = reinterpret_cast<const float2*>(d_x);
+
+  const int64_t n_pend = s->L - s->nc;
+  const int64_t L_new = s->L + n;
+  const int64_t n_used_new = std::max<int64_t>(0, L_new - s->T + 1);
+  const int64_t chunks_new = n_used_new / s->Kc - s->nc / s->Kc;
+
+  VSrc v;
+  v.pend = s->pend[s->cur];
+  v.xin = x;
+  v.n_pend = n_pend;
+  v.n_avail = n_pend + n;
+
+  for (int64_t done = 0; done < chunks_new;) {
+    const int nch = (int)std::min<int64_t>(s->maxc, chunks_new - done);
+    const int64_t abs0 = s->nc + done * s->Kc;
+    if (launch_phase(s->alpha_r, s->A, abs0, s->Kc, nch, s->E, st) != hipSuccess ||
+        run_contract(s, v, done * s->Kc, (int64_t)nch * s->Kc, nch, st) != hipSuccess ||
+        launch_accumulate(s->S, s->part, s->E, s->T, s->A, nch, abs0 == 0 ? 1 : 0, st) != hipSuccess)
+      return fail_device(s);
+    done += nch;
+  }
+
+  const int64_t shift = chunks_new * s->Kc;
+  const int64_t n_pend_new = n_pend + n - shift;
+  if (shift == 0) {
+    // append the new samples behind the pending ones
+    VSrc src;
+    src.pend = x;
+    src.xin = nullptr;
+    src.n_pend = n;
+    src.n_avail = n;
+    if (launch_vcopy(src, 0, n, s->pend[s->cur] + n_pend, st) != hipSuccess) return fail_device(s);
+  } else {
+    if (launch_vcopy(v, shift, n_pend_new, s->pend[s->cur ^ 1], st) != hipSuccess)
+      return fail_device(s);
+    s->cur ^= 1;
+  }
+  s->L = L_new;
+  s->nc += shift;
+  return CYC_OK;
+}
+
+int cyc_read(cyc_state* s, void* d_R, void* d_Rc, int64_t* n_used, void* stream) {
+  if (!s) return CYC_EINVAL;
+  if (s->poisoned) return CYC_ESTATE;
+  hipStream_t st = as_stream(stream);
+  const int c128 = (s->flags & CYC_OUT_C128) ? 1 : 0;
+  const int64_t tbytes = (int64_t)s->T * s->A * (c128 ? 16 : 8);
+  const int64_t nu = std::max<int64_t>(0, s->L - s->T + 1);
+  if (n_used) *n_used = nu;
+  if (!d_R && !d_Rc) return CYC_OK;
+  if (nu == 0) {
+    if ((d_R && launch_zero(d_R, tbytes, st) != hipSuccess) ||
+        (d_Rc && launch_zero(d_Rc, tbytes, st) != hipSuccess))
+      return fail_device(s);
+    return CYC_OK;
+  }
+  const int64_t m = nu - s->nc;  // products of the pending partial chunk, < Kc
+  if (m > 0) {
+    VSrc v;
+    v.pend = s->pend[s->cur];
+    v.xin = nullptr;
+    v.n_pend = s->L - s->nc;
+    v.n_avail = v.n_pend;
+    if (launch_phase(s->alpha_r, s->A, s->nc, s->Kc, 1, s->E, st) != hipSuccess ||
+        run_contract(s, v, 0, m, 1, st) != hipSuccess)
+      return fail_device(s);
+  }
+  if (launch_finalize(s->S, s->nc > 0 ? 1 : 0, s->part, s->E, m > 0 ? 1 : 0, s->T, s->A, nu, d_R,
+                      d_Rc, c128, st) != hipSuccess)
+    return fail_device(s);
+  return CYC_OK;
+}
+
+int cyc_reset(cyc_state* s) {
+  if (!s) return CYC_EINVAL;
+  s->L = 0;
+  s->nc = 0;
+  s->cur = 0;
+  s->poisoned = false;
+  return CYC_OK;
+}
+
+void cyc_destroy(cyc_state* s) {
+  if (!s) return;
+  (void)hipDeviceSynchronize();
+  free_state(s);
+}
+
+int cyc_profile(cyc_state* s, int32_t enable) {
+  if (!s) return CYC_EINVAL;
+  s->prof = enable != 0;
+  if (s->prof) {
+    s->ev_used = 0;
+    s->prof_work = 0.0;
+  }
+  return CYC_OK;
+}
+
+int cyc_profile_read(cyc_state* s, double* total_ms, int64_t* launches, double* work) {
+  if (!s) return CYC_EINVAL;
+  double ms = 0.0;
+  for (size_t i = 0; i + 1 < s->ev_used; i += 2) {
+    float t = 0.f;
+    if (hipEventSynchronize(s->ev[i + 1]) != hipSuccess ||
+        hipEventElapsedTime(&t, s->ev[i], s->ev[i + 1]) != hipSuccess)
+      return CYC_EDEVICE;
+    ms += t;
+  }
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = (int64_t)(s->ev_used / 2);
+  if (work) *work = s->prof_work;
+  return CYC_OK;
+}
+
+int cyc_query(const cyc_state* s, int64_t* n_pushed, int64_t* n_committed, int32_t* chunk,
+              int32_t* kernel_cfg) {
+  if (!s) return CYC_EINVAL;
+  if (n_pushed) *n_pushed = s->L;
+  if (n_committed) *n_committed = s->nc;
+  if (chunk) *chunk = s->Kc;
+  if (kernel_cfg) *kernel_cfg = s->cfg;
+  return CYC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,196 @@
+"""ctypes binding of libcyclo.so (C ABI in include/cyclo.h).
+
+Argument marshalling only: every step of the estimator runs in the HIP
+library.  Device buffers are torch tensors (used for memory and streams).  If
+the library is not built this module raises on first use; there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcyclo.so")
+
+CYC_OK = 0
+CYC_EINVAL = -1
+CYC_ENOMEM = -2
+CYC_EDEVICE = -3
+CYC_ESTATE = -4
+CYC_EUNSUPPORTED = -5
+
+CYC_OP_FP32 = 0x0
+CYC_OP_BF16 = 0x1
+CYC_OP_FP16 = 0x2
+CYC_TW_SPLIT = 0x4
+CYC_OUT_C128 = 0x8
+
+#: exported symbols and their ctypes signatures (restype, argtypes)
+SIGNATURES = {
+    "cyc_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p]),
+    "cyc_push": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "cyc_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+    "cyc_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "cyc_destroy": (None, [ctypes.c_void_p]),
+    "cyc_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "cyc_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_int32)]),
+    "cyc_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "cyc_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
+}
+
+_lib = None
+
+
+class CycloError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {status_str(code)} ({code})")
+        self.code = code
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libcyclo.so once; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2405_16911_amd.build "
+                               "(the estimator has no non-HIP implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_str(code: int) -> str:
+    return lib().cyc_status_str(int(code)).decode()
+
+
+def _check(code: int, where: str):
+    if code != CYC_OK:
+        raise CycloError(code, where)
+
+
+def _stream_handle(stream) -> int | None:
+    """hipStream_t of a torch stream (None -> torch's current stream)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream or None
+
+
+# ----------------------------------------------------------------------------- same-name calls
+
+def cyc_create(alphas, n_lag: int, flags: int = 0, stream=None) -> ctypes.c_void_p:
+    a = np.ascontiguousarray(np.asarray(alphas, dtype=np.float64).reshape(-1))
+    out = ctypes.c_void_p()
+    code = lib().cyc_create(ctypes.byref(out), a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                            int(a.size), int(n_lag), int(flags), _stream_handle(stream))
+    _check(code, "cyc_create")
+    return out
+
+
+def cyc_push(state, x, stream=None):
+    """x: 1-D contiguous torch.complex64 tensor on the GPU."""
+    import torch
+    if x.dtype != torch.complex64 or not x.is_cuda or not x.is_contiguous() or x.dim() != 1:
+        raise ValueError("x must be a contiguous 1-D complex64 CUDA tensor")
+    _check(lib().cyc_push(state, ctypes.c_void_p(x.data_ptr()) if x.numel() else None,
+                          int(x.numel()), _stream_handle(stream)), "cyc_push")
+
+
+def cyc_read(state, R=None, Rc=None, stream=None) -> int:
+    """Writes the tables into the given [T, A] tensors (either may be None); returns N_used."""
+    n_used = ctypes.c_int64(0)
+    pr = ctypes.c_void_p(R.data_ptr()) if R is not None else None
+    prc = ctypes.c_void_p(Rc.data_ptr()) if Rc is not None else None
+    _check(lib().cyc_read(state, pr, prc, ctypes.byref(n_used), _stream_handle(stream)), "cyc_read")
+    return int(n_used.value)
+
+
+def cyc_reset(state):
+    _check(lib().cyc_reset(state), "cyc_reset")
+
+
+def cyc_destroy(state):
+    lib().cyc_destroy(state)
+
+
+def cyc_status_str(code: int) -> str:
+    return status_str(code)
+
+
+def cyc_query(state) -> dict:
+    n, c = ctypes.c_int64(), ctypes.c_int64()
+    k, cfg = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().cyc_query(state, ctypes.byref(n), ctypes.byref(c), ctypes.byref(k), ctypes.byref(cfg)),
+           "cyc_query")
+    return dict(n_pushed=n.value, n_committed=c.value, chunk=k.value, kernel_cfg=cfg.value)
+
+
+def cyc_profile(state, enable: bool):
+    _check(lib().cyc_profile(state, 1 if enable else 0), "cyc_profile")
+
+
+def cyc_profile_read(state) -> dict:
+    ms, n, w = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    _check(lib().cyc_profile_read(state, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(w)),
+           "cyc_profile_read")
+    return dict(total_ms=ms.value, launches=n.value, work=w.value)
+
+
+# ----------------------------------------------------------------------------- convenience wrapper
+
+class CyclicStream:
+    """One streaming estimator state on the current GPU."""
+
+    def __init__(self, alphas, n_lag: int, flags: int = 0, stream=None):
+        self.alphas = np.asarray(alphas, dtype=np.float64).reshape(-1)
+        self.T = int(n_lag)
+        self.flags = int(flags)
+        self._s = cyc_create(self.alphas, self.T, self.flags, stream)
+
+    def push(self, x, stream=None):
+        cyc_push(self._s, x, stream)
+
+    def read(self, stream=None, which=(True, True)):
+        """Returns (R, Rc, n_used) as new [T, A] complex tensors on the GPU."""
+        import torch
+        dt = torch.complex128 if self.flags & CYC_OUT_C128 else torch.complex64
+        shape = (self.T, self.alphas.size)
+        R = torch.empty(shape, dtype=dt, device="cuda") if which[0] else None
+        Rc = torch.empty(shape, dtype=dt, device="cuda") if which[1] else None
+        n = cyc_read(self._s, R, Rc, stream)
+        return R, Rc, n
+
+    def reset(self):
+        cyc_reset(self._s)
+
+    def query(self) -> dict:
+        return cyc_query(self._s)
+
+    def profile(self, enable: bool):
+        cyc_profile(self._s, enable)
+
+    def profile_read(self) -> dict:
+        return cyc_profile_read(self._s)
+
+    def close(self):
+        if self._s is not None:
+            cyc_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,75 @@
+"""The C-ABI library loads, exports every symbol that include/cyclo.h declares,
+and rejects bad arguments before touching the device (no GPU needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2405_16911_amd import cyclo
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            src = open(os.path.join(inc, fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"^[A-Za-z_][\w\s\*]*?\b(cyc_\w+)\s*\(", src, flags=re.M))
+    return names
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(cyclo.LIB_PATH):
+        from paper_2405_16911_amd.build import build_library
+        build_library()
+    return cyclo.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert {"cyc_create", "cyc_push", "cyc_read", "cyc_reset", "cyc_destroy", "cyc_status_str",
+            "cyc_query"} <= names
+    out = subprocess.run(["nm", "-D", "--defined-only", cyclo.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r"\bT (cyc_\w+)", out))
+    assert names <= exported, names - exported
+    assert set(cyclo.SIGNATURES) == names
+    for n in names:
+        getattr(L, n)
+
+
+def test_status_strings(L):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert cyclo.status_str(code)
+    assert "unknown" in cyclo.status_str(42)
+
+
+def test_invalid_arguments_rejected_on_host(L):
+    out = ctypes.c_void_p()
+    a = (ctypes.c_double * 3)(0.0, 0.1, 0.2)
+    assert L.cyc_create(None, a, 3, 4, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_create(ctypes.byref(out), None, 3, 4, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_create(ctypes.byref(out), a, 0, 4, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_create(ctypes.byref(out), a, 3, 0, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_create(ctypes.byref(out), a, 3, 5000, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_create(ctypes.byref(out), a, 3, 4, 0x100, None) == cyclo.CYC_EINVAL
+    assert L.cyc_create(ctypes.byref(out), a, 3, 4, 0x3, None) == cyclo.CYC_EINVAL
+    assert L.cyc_create(ctypes.byref(out), a, 3, 4, cyclo.CYC_TW_SPLIT, None) == cyclo.CYC_EUNSUPPORTED
+    bad = (ctypes.c_double * 2)(0.0, float("nan"))
+    assert L.cyc_create(ctypes.byref(out), bad, 2, 4, 0, None) == cyclo.CYC_EINVAL
+    inf = (ctypes.c_double * 1)(float("inf"))
+    assert L.cyc_create(ctypes.byref(out), inf, 1, 4, 0, None) == cyclo.CYC_EINVAL
+    assert out.value is None
+    assert L.cyc_push(None, None, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_read(None, None, None, None, None) == cyclo.CYC_EINVAL
+    assert L.cyc_reset(None) == cyclo.CYC_EINVAL
+    assert L.cyc_query(None, None, None, None, None) == cyclo.CYC_EINVAL
+    assert L.cyc_profile(None, 1) == cyclo.CYC_EINVAL
+    assert L.cyc_profile_read(None, None, None, None) == cyclo.CYC_EINVAL
+    L.cyc_destroy(None)

@@ -1,0 +1,219 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Error measure (per table entry): scaled error |Rhat - R| / s_t with
+s_t = (1/N_used) sum_n |x[n+t]| |x[n]|, the condition scale of the length-N
+dot product behind each entry (so entries where R is near zero are judged
+against what rounding can actually do there).  Tolerances:
+  FP32 operands                       <= 1e-5
+  BF16 operands (u = 2^-8)            <= 2^-7   (a-priori bound 2u)
+  FP16 operands (u = 2^-11)           <= 2^-10
+  split modulated operand, BF16/FP16  <= same bounds (measured errors reported)
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle.cyclic import cyclic_cell, cyclic_tables, scale_per_lag
+from paper_2405_16911_amd import siggen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-5, 1: 2.0 ** -7, 2: 2.0 ** -10}
+
+
+@pytest.fixture(scope="module")
+def cy():
+    from paper_2405_16911_amd import cyclo
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    cyclo.lib()
+    return cyclo
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def _run(cy, x, alphas, T, flags=0, splits=None, env=None):
+    old = {}
+    for k, v in (env or {}).items():
+        old[k] = os.environ.get(k)
+        os.environ[k] = str(v)
+    try:
+        st = cy.CyclicStream(alphas, T, flags)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    xd = _dev(x)
+    pos = 0
+    for n in (splits or [x.size]):
+        st.push(xd[pos:pos + n])
+        pos += n
+    assert pos == x.size
+    R, Rc, n = st.read()
+    torch.cuda.synchronize()
+    q = st.query()
+    st.close()
+    return R.cpu().numpy(), Rc.cpu().numpy(), n, q
+
+
+def _scaled_err(got, ref, s):
+    return np.abs(got.astype(np.complex128) - ref) / s[:, None]
+
+
+def _check(x, alphas, T, R, Rc, n, tol, chunk=4096):
+    Ro, Rco, no = cyclic_tables(x, alphas, T, chunk=chunk)
+    assert n == no
+    s = scale_per_lag(x, T)
+    e = max(_scaled_err(R, Ro, s).max(), _scaled_err(Rc, Rco, s).max())
+    print(f"  max scaled error {e:.3e} (tol {tol:.1e})", flush=True)
+    assert e <= tol, e
+    return e
+
+
+def test_config1_gmsk_fp32(cy):
+    """GMSK 32768 samples, T = 32, alpha = k/128 (the small single-stream workload)."""
+    x = siggen.gmsk_stream(n=32768, seed=1)
+    alphas = np.arange(128) / 128
+    R, Rc, n, _ = _run(cy, x, alphas, 32)
+    _check(x, alphas, 32, R, Rc, n, TOL[0])
+
+
+@pytest.mark.parametrize("flags,prec", [(1, 1), (2, 2), (1 | 4, 1), (2 | 4, 2)])
+def test_config1_low_precision(cy, flags, prec):
+    x = siggen.gmsk_stream(n=32768, seed=1)
+    alphas = np.arange(128) / 128
+    R, Rc, n, _ = _run(cy, x, alphas, 32, flags=flags)
+    _check(x, alphas, 32, R, Rc, n, TOL[prec])
+
+
+@pytest.mark.parametrize("flags", [0, 1, 2, 5])
+@pytest.mark.parametrize("T,A", [(37, 150), (128, 70), (5, 1), (257, 66)])
+def test_ragged_shapes(cy, flags, T, A):
+    """Lag/alpha counts that are not tile multiples; several chunks plus a ragged tail."""
+    rng = np.random.default_rng(T * 1000 + A)
+    L = 3 * 4096 + 123 + T
+    x = siggen.qpsk_rrc_stream(n=L, seed=3)
+    alphas = rng.uniform(-2.0, 2.0, size=A)
+    alphas[0] = 0.0
+    R, Rc, n, q = _run(cy, x, alphas, T, flags=flags, splits=[1000, 5000, 1, 7000, L - 13001])
+    assert q["n_committed"] == ((L - T + 1) // q["chunk"]) * q["chunk"]
+    _check(x, alphas, T, R, Rc, n, TOL[flags & 3])
+
+
+def test_segmentation_bitwise_and_determinism(cy):
+    x = siggen.gmsk_stream(n=20000, seed=5)
+    alphas = np.arange(96) / 96 - 0.5
+    T = 24
+    ref = _run(cy, x, alphas, T)
+    again = _run(cy, x, alphas, T)
+    assert np.array_equal(ref[0], again[0]) and np.array_equal(ref[1], again[1])
+    rng = np.random.default_rng(0)
+    for trial in range(3):
+        cuts = np.sort(rng.choice(np.arange(1, x.size), size=10 + trial * 20, replace=False))
+        splits = np.diff(np.concatenate([[0], cuts, [x.size]])).tolist()
+        got = _run(cy, x, alphas, T, splits=splits)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), trial
+    # pushes shorter than T, one sample at a time for the first 3*T samples
+    splits = [1] * (3 * T) + [x.size - 3 * T]
+    got = _run(cy, x, alphas, T, splits=splits)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
+def test_small_chunks_many_commits(cy):
+    x = siggen.gmsk_stream(n=5000, seed=6)
+    alphas = np.arange(40) / 40
+    T = 9
+    R, Rc, n, q = _run(cy, x, alphas, T, env={"CYC_CHUNK": 64}, splits=[100, 1, 2000, 2899])
+    assert q["chunk"] == 64
+    _check(x, alphas, T, R, Rc, n, TOL[0])
+    # workspace limited to one chunk per launch
+    R2, Rc2, n2, _ = _run(cy, x, alphas, T, env={"CYC_CHUNK": 64, "CYC_WORKSPACE_MB": 0})
+    assert np.array_equal(R, R2) and np.array_equal(Rc, Rc2)
+
+
+def test_edge_cases(cy):
+    alphas = np.array([0.0, 0.25, -0.125])
+    T = 8
+    x = siggen.gmsk_stream(n=64, seed=7)
+    st = cy.CyclicStream(alphas, T)
+    R, Rc, n = st.read()
+    assert n == 0 and not R.abs().sum().item() and not Rc.abs().sum().item()
+    xd = _dev(x)
+    st.push(xd[:0])
+    st.push(xd[:T - 1])
+    R, Rc, n = st.read()
+    assert n == 0 and not R.abs().sum().item()
+    st.push(xd[T - 1:T])
+    R, Rc, n = st.read()
+    torch.cuda.synchronize()
+    assert n == 1
+    Ro, Rco, _ = cyclic_tables(x[:T], alphas, T)
+    assert np.max(np.abs(R.cpu().numpy() - Ro)) < 1e-5 * np.max(np.abs(Ro))
+    # reset == fresh state
+    st.push(xd[T:])
+    st.reset()
+    st.push(xd)
+    R1, Rc1, n1 = st.read()
+    fresh = cy.CyclicStream(alphas, T)
+    fresh.push(xd)
+    R2, Rc2, n2 = fresh.read()
+    torch.cuda.synchronize()
+    assert n1 == n2 == x.size - T + 1
+    assert torch.equal(R1, R2) and torch.equal(Rc1, Rc2)
+    # read one table only
+    Ronly, none, _ = st.read(which=(True, False))
+    assert none is None and torch.equal(Ronly, R1)
+    st.close()
+    fresh.close()
+
+
+def test_complex128_output(cy):
+    x = siggen.gmsk_stream(n=9000, seed=8)
+    alphas = np.arange(32) / 32
+    R, Rc, n, _ = _run(cy, x, alphas, 16, flags=8)
+    assert R.dtype == np.complex128
+    _check(x, alphas, 16, R, Rc, n, TOL[0])
+
+
+def test_abi_errors_on_device(cy):
+    import ctypes
+    st = cy.CyclicStream([0.1], 4)
+    L = cy.lib()
+    assert L.cyc_push(st._s, None, 5, None) == cy.CYC_EINVAL
+    assert L.cyc_push(st._s, None, -1, None) == cy.CYC_EINVAL
+    assert L.cyc_push(st._s, None, 0, None) == cy.CYC_OK
+    n = ctypes.c_int64(-1)
+    assert L.cyc_read(st._s, None, None, ctypes.byref(n), None) == cy.CYC_OK and n.value == 0
+    st.close()
+
+
+def test_config2_full_size_sampled_cells(cy):
+    """QPSK-RRC 2^24 samples, T = 128, 4096 alphas in [-1/2, 1/2), 256 pushes of 65536.
+
+    Sampled cells (features at alpha = 0, +-1/4 and random cells) are checked
+    one by one against the oracle's direct sum over the whole record.
+    """
+    L, T, A, blk = 1 << 24, 128, 4096, 65536
+    x = siggen.qpsk_rrc_stream(n=L)
+    alphas = siggen.uniform_grid(A, -0.5)
+    R, Rc, n, q = _run(cy, x, alphas, T, splits=[blk] * (L // blk))
+    assert n == L - T + 1
+    rng = np.random.default_rng(2)
+    cells = [(0, 2048), (1, 2048), (4, 1024), (4, 3072), (127, 2048), (64, 0), (3, 2049)]
+    cells += [(int(rng.integers(0, T)), int(rng.integers(0, A))) for _ in range(9)]
+    s = scale_per_lag(x, T)
+    worst = 0.0
+    for t, j in cells:
+        r, rc = cyclic_cell(x, alphas[j], t, T)
+        e = max(abs(R[t, j] - r), abs(Rc[t, j] - rc)) / s[t]
+        worst = max(worst, e)
+    print(f"  config-2 sampled max scaled error {worst:.3e}", flush=True)
+    assert worst <= TOL[0]
+    # the strongest features of QPSK-RRC at 4 samples/symbol: alpha = 0 and +-1/4
+    m = np.abs(R[2])
+    assert set(np.argsort(-m)[:3]) == {2048, 1024, 3072}
