@@ -45,13 +45,14 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_gpu(wl, prec: str, split: bool, steps: int, warmup: int):
+def run_gpu(wl, prec: str, split: bool, steps: int, warmup: int, autotune: bool = True):
     import torch
     from paper_2405_16911_amd import cyclo
     flags = PREC_FLAGS[prec] | (cyclo.CYC_TW_SPLIT if split else 0)
     x = torch.from_numpy(wl["x"]).to("cuda")
     T, alphas, blk = wl["T"], wl["alphas"], wl["block"]
     A = alphas.size
+    tuned = cyclo.cyc_autotune(alphas.size, T, flags) if autotune else None
     st = cyclo.CyclicStream(alphas, T, flags)
     R = torch.empty((T, A), dtype=torch.complex64, device="cuda")
     Rc = torch.empty_like(R)
@@ -77,7 +78,8 @@ def run_gpu(wl, prec: str, split: bool, steps: int, warmup: int):
     q = st.query()
     st.close()
     triples = float(A) * T * n_used
-    return dict(sec_per_step=dt, n_used=n_used, triples=triples, prof=prof, query=q)
+    q["kernel_cfg_name"] = cyclo.cyc_kernel_cfg_info(q["kernel_cfg"])["name"]
+    return dict(sec_per_step=dt, n_used=n_used, triples=triples, prof=prof, query=q, tuned=tuned)
 
 
 def cpu_baseline(wl, n_samples: int):
@@ -106,6 +108,17 @@ def cpu_baseline(wl, n_samples: int):
                        f"host {platform.processor() or platform.machine()}")
 
 
+def copy_calibration(nbytes: int = 256 << 20, reps: int = 5):
+    """A plain copy kernel of known size: reads and writes nbytes per launch."""
+    import torch
+    src = torch.rand(nbytes // 4, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_launch": nbytes, "launches": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,14 +131,20 @@ def main():
                     help="extra precision forms timed after the main one ('' for none)")
     ap.add_argument("--cpu-samples", type=int, default=1 << 21)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain elementwise copy of 256 MiB (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; multi-GPU sharding is "
                                    "a design note, not an implemented path", "n_gpus": args.gpus}))
         raise SystemExit(2)
 
     wl = workload(args.workload)
-    main_run = run_gpu(wl, args.precision, args.split, args.steps, args.warmup)
+    main_run = run_gpu(wl, args.precision, args.split, args.steps, args.warmup, not args.no_autotune)
     prof = main_run["prof"]
     kernel_ms = prof["total_ms"] / max(1, prof["launches"])
     achieved = FLOPS_PER_TRIPLE * prof["work"] / (prof["total_ms"] * 1e-3) / 1e12
@@ -137,9 +156,10 @@ def main():
         prec, split = v.rstrip("s"), v.endswith("s")
         if prec == args.precision and split == args.split:
             continue
-        r = run_gpu(wl, prec, split, max(2, args.steps), 1)
+        r = run_gpu(wl, prec, split, max(2, args.steps), 1, not args.no_autotune)
         p = r["prof"]
         variants.append(dict(dtype=prec, split=split, value=r["triples"] / r["sec_per_step"],
+                             kernel_cfg=r["query"]["kernel_cfg_name"],
                              ms_per_step=1e3 * r["sec_per_step"],
                              kernel_tflops=FLOPS_PER_TRIPLE * p["work"] / (p["total_ms"] * 1e-3) / 1e12,
                              kernel_frac=(FLOPS_PER_TRIPLE * p["work"] / (p["total_ms"] * 1e-3) / 1e12)
@@ -153,7 +173,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "n_samples": int(wl["x"].size), "n_lag": wl["T"],
                    "n_alpha": int(wl["alphas"].size), "push_block": wl["block"],
-                   "chunk": main_run["query"]["chunk"], "kernel_cfg": main_run["query"]["kernel_cfg"]},
+                   "chunk": main_run["query"]["chunk"], "kernel_cfg": main_run["query"]["kernel_cfg_name"],
+                   "autotuned": main_run["tuned"] is not None},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
                      "kernel": "contract (chunk contraction)", "kernel_ms_avg": kernel_ms,

@@ -132,6 +132,40 @@ int cyc_query(const cyc_state* s, int64_t* n_pushed, int64_t* n_committed,
 int cyc_profile(cyc_state* s, int32_t enable);
 int cyc_profile_read(cyc_state* s, double* total_ms, int64_t* launches, double* work);
 
+/*
+ * Contraction-kernel configurations (tile shapes).  Index idx in
+ * [0, cyc_kernel_cfg_count()).  cyc_kernel_cfg_info reports the operand
+ * precision and split flags the configuration implements (CYC_OP_* |
+ * CYC_TW_SPLIT), its lag and cycle-frequency tile, its workgroup size and a
+ * static name; outputs may be NULL.  Errors: CYC_EINVAL (idx out of range).
+ */
+int cyc_kernel_cfg_count(void);
+int cyc_kernel_cfg_info(int32_t idx, uint32_t* flags, int32_t* lag_tile, int32_t* alpha_tile,
+                        int32_t* threads, const char** name);
+
+/*
+ * Use configuration idx for the state's contraction from now on.  Every
+ * configuration of one precision evaluates each table entry with the same
+ * operands in the same order, so switching does not change results.
+ * Errors: CYC_EINVAL (s NULL, idx out of range), CYC_EUNSUPPORTED (idx
+ * implements another precision or split mode).
+ */
+int cyc_set_kernel_cfg(cyc_state* s, int32_t idx);
+
+/*
+ * Autotuner.  Times every configuration that implements `flags` on one push of
+ * synthetic samples into a state of n_alpha cycle frequencies and n_lag lags
+ * (HIP events on `stream`), and records the fastest in the tuning cache under
+ * (device architecture, precision, split, n_lag, ceil(log2 n_alpha)).
+ * cyc_create consults the cache.  If the environment variable CYC_TUNE_CACHE
+ * names a file, the cache is loaded from it on first use and every new entry
+ * is appended to it (one line per entry).  best_cfg / best_ms (may be NULL)
+ * receive the winner and its time per push.  Allocates and frees device
+ * memory.  Errors: as cyc_create, plus CYC_EDEVICE.
+ */
+int cyc_autotune(int32_t n_alpha, int32_t n_lag, uint32_t flags, int32_t* best_cfg, double* best_ms,
+                 void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,5 +58,6 @@ hipError_t launch_finalize(const double2* S, int hasS, const float2* part0, cons
                            hipStream_t st);
 hipError_t launch_vcopy(VSrc v, int64_t shift, int64_t n, float2* dst, hipStream_t st);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
+hipError_t launch_pattern(float2* x, int64_t n, hipStream_t st);
 
 }  // namespace cyclo

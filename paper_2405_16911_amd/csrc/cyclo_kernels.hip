@@ -34,9 +34,9 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // ----------------------------------------------------------------------------- helpers
 
 __device__ __forceinline__ float2 vload(const VSrc& v, int64_t g) {
-  if (g < v.n_pend) return v.pend[g];
-  if (g < v.n_avail) return v.xin[g - v.n_pend];
-  return make_float2(0.f, 0.f);
+  if (g >= v.n_avail) return make_float2(0.f, 0.f);
+  const float2* p = g < v.n_pend ? v.pend + g : v.xin + (g - v.n_pend);
+  return *p;
 }
 
 __device__ __forceinline__ float2 cmul(float2 p, float2 q) {
@@ -134,10 +134,86 @@ __device__ __forceinline__ void store_tiles(const ContractArgs& a, const TileId&
   }
 }
 
+// ----------------------------------------------------------------------------- sample staging
+//
+// Each K step of KS products needs the Hankel window Xh[p] = x[s0 + tau0 + p]
+// (p < XW) and the modulated-operand samples Xy[j] = x[s0 + j] (j < KS), the
+// latter zeroed for products at or beyond the chunk's product count so the
+// modulated operands of a partial last step vanish without per-element masks.
+// The global loads for step ks+2 (and its twiddle-table entry) are issued
+// before the matrix-core work of step ks and written to LDS after it, so their
+// latency is hidden.  Loads are bounds-checked, so the steady-state loop can
+// stage a window past the last step without branching.
+template <int NT, int XW, int KS>
+struct Stager {
+  static constexpr int N = XW + KS;
+  static constexpr int R = (N + NT - 1) / NT;
+  float2 r[R];
+  float2 hv;
+  __device__ __forceinline__ void load(const VSrc& v, int64_t s0, int tau0, int64_t yend,
+                                       const float2* hp, int tid) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int idx = tid + i * NT;
+      if (idx < XW) {
+        r[i] = vload(v, s0 + tau0 + idx);
+      } else if (idx < N) {
+        const int64_t g = s0 + (idx - XW);
+        r[i] = g < yend ? vload(v, g) : make_float2(0.f, 0.f);
+      }
+    }
+    hv = *hp;
+  }
+  __device__ __forceinline__ void store(float2* Xh, float2* Xy, int tid) const {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int idx = tid + i * NT;
+      if (idx < XW)
+        Xh[idx] = r[i];
+      else if (idx < N)
+        Xy[idx - XW] = r[i];
+    }
+  }
+};
+
+// Modulated operands of one thread: G consecutive samples of one alpha.
+// W = H * Lo, Y = conj(x) W, Yc = x W.
+template <int G>
+__device__ __forceinline__ void modulate(const float2* xs, float2 hv, const float2 (&lo)[G],
+                                         float2 (&y)[G], float2 (&yc)[G]) {
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const float2 xv = xs[g];
+    const float2 w = cmul(hv, lo[g]);
+    const float t1 = xv.y * w.y, t2 = xv.y * w.x;
+    y[g] = make_float2(__fmaf_rn(xv.x, w.x, t1), __fmaf_rn(xv.x, w.y, -t2));
+    yc[g] = make_float2(__fmaf_rn(xv.x, w.x, -t1), __fmaf_rn(xv.x, w.y, t2));
+  }
+}
+
+// Common per-workgroup set-up.
+struct Tile {
+  TileId id;
+  int tau0, alpha0, ns, nsteps;
+  int64_t cbase, yend;
+  __device__ __forceinline__ Tile(const ContractArgs& a, int tw, int aw, int ks) {
+    id = tile_of(a);
+    tau0 = id.tt * tw;
+    alpha0 = id.at * aw;
+    cbase = a.v_off + (int64_t)id.chunk * a.Kc;
+    const int64_t mprod = min((int64_t)a.Kc, a.n_prod - (int64_t)id.chunk * a.Kc);
+    yend = cbase + mprod;
+    nsteps = a.Kc / ks;
+    ns = (int)((mprod + ks - 1) / ks);
+  }
+};
+
 // ----------------------------------------------------------------------------- FP32 contraction
 //
 // v_mfma_f32_32x32x2f32: one complex sample per instruction (K' = 2 = re, im).
 // A lane holds A'[row = lane%32][k = lane/32] and B'[k = lane/32][col = lane%32].
+// Hankel value for row (t, cr) and component c: component (cr ^ c) of
+// x[s0+l+t], negated for cr = 0, c = 1.
 template <int TW, int AW, int WAVES_M, int WAVES_N, int KS>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_f32(ContractArgs a) {
   constexpr int NT = 64 * WAVES_M * WAVES_N;
@@ -145,53 +221,51 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_f32(Contra
   constexpr int WM = MR / (32 * WAVES_M), WN = NC / (32 * WAVES_N);
   static_assert(WM * 32 * WAVES_M == MR && WN * 32 * WAVES_N == NC, "tile");
   constexpr int G = KS * AW / NT;
-  static_assert(G >= 1 && G * NT == KS * AW && KS % G == 0, "B-gen split");
-  constexpr int XP = TW + KS;  // staged samples per step
+  static_assert(G >= 2 && G % 2 == 0 && G * NT == KS * AW && KS % G == 0, "B-gen split");
+  constexpr int XW = TW + KS;
 
-  __shared__ __attribute__((aligned(16))) float4 Xs[2][XP];     // (re, -im, im, re)
+  // The matrix-core loop reads the Hankel values straight from the staged
+  // window, so it is triple-buffered: the window of step ks+2 is written while
+  // slower waves may still read the one of step ks.
+  __shared__ __attribute__((aligned(16))) float2 Xh[3][XW];
+  __shared__ __attribute__((aligned(16))) float2 Xy[2][KS];
   __shared__ __attribute__((aligned(16))) float2 Bs[2][KS][NC];  // [j][q] = (re, im)
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
   const int h = lane >> 5, l32 = lane & 31;
-  const TileId id = tile_of(a);
-  const int tau0 = id.tt * TW, alpha0 = id.at * AW;
-  const int64_t cbase = a.v_off + (int64_t)id.chunk * a.Kc;
-  const int64_t mprod = min((int64_t)a.Kc, a.n_prod - (int64_t)id.chunk * a.Kc);
-  const int nsteps = a.Kc / KS;
-  const int nsteps_eff = (int)((mprod + KS - 1) / KS);
+  const Tile tl(a, TW, AW, KS);
+  const int ns = tl.ns;
 
-  // modulated-operand generator role: one alpha, G consecutive samples
   const int ga = tid % AW, gj = (tid / AW) * G;
-  const int galpha = alpha0 + ga;
+  const int galpha = tl.alpha0 + ga;
   const bool aval = galpha < a.A;
   float2 lo[G];
 #pragma unroll
   for (int g = 0; g < G; ++g)
     lo[g] = aval ? a.Lo[(int64_t)galpha * KS + gj + g] : make_float2(0.f, 0.f);
-  const float2* Hrow = a.H + (int64_t)(aval ? galpha : 0) * nsteps;
+  const float2* Hrow = a.H + (int64_t)(aval ? galpha : 0) * tl.nsteps;
+  auto hptr = [&](int ks) { return Hrow + min(ks, tl.nsteps - 1); };
 
-  auto produce = [&](int ks, int buf) {
-    const int64_t s0 = cbase + (int64_t)ks * KS;
-    for (int p = tid; p < XP; p += NT) {
-      const float2 v = vload(a.v, s0 + tau0 + p);
-      Xs[buf][p] = make_float4(v.x, -v.y, v.y, v.x);
-    }
-    const float2 hv = aval ? Hrow[ks] : make_float2(0.f, 0.f);
+  int xoff[WM];
+  uint32_t xneg[WM];
+#pragma unroll
+  for (int rb = 0; rb < WM; ++rb) {
+    const int R = (wm * WM + rb) * 32 + l32;
+    const int cr = R & 1;
+    xoff[rb] = 2 * (R >> 1) + (cr ^ h);
+    xneg[rb] = (cr == 0 && h == 1) ? 0x80000000u : 0u;
+  }
+
+  auto produce = [&](int buf, float2 hv) {
+    float2 y[G], yc[G];
+    modulate<G>(&Xy[buf][gj], hv, lo, y, yc);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      const int j = gj + g;
-      const bool valid = aval && ((int64_t)ks * KS + j < mprod);
-      const float2 xv = vload(a.v, s0 + j);
-      const float2 w = cmul(hv, lo[g]);
-      float2 y = make_float2(xv.x * w.x + xv.y * w.y, xv.x * w.y - xv.y * w.x);
-      float2 yc = make_float2(xv.x * w.x - xv.y * w.y, xv.x * w.y + xv.y * w.x);
-      if (!valid) y = yc = make_float2(0.f, 0.f);
-      Bs[buf][j][ga] = y;
-      Bs[buf][j][AW + ga] = yc;
+      Bs[buf][gj + g][ga] = y[g];
+      Bs[buf][gj + g][AW + ga] = yc[g];
     }
   };
-
   f32x16 acc[WM][WN];
 #pragma unroll
   for (int i = 0; i < WM; ++i)
@@ -199,33 +273,51 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_f32(Contra
     for (int k = 0; k < WN; ++k)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][k][v] = 0.f;
-
-  if (nsteps_eff > 0) produce(0, 0);
-  __syncthreads();
-  for (int ks = 0; ks < nsteps_eff; ++ks) {
-    const int buf = ks & 1;
+  auto mfma_step = [&](int xbuf, int buf) {
+    const float* xf = reinterpret_cast<const float*>(&Xh[xbuf][0]);
 #pragma unroll 4
     for (int j = 0; j < KS; ++j) {
       float af[WM], bf[WN];
 #pragma unroll
-      for (int rb = 0; rb < WM; ++rb) {
-        const int R = (wm * WM + rb) * 32 + l32;
-        af[rb] = reinterpret_cast<const float*>(&Xs[buf][0])[4 * (j + (R >> 1)) + 2 * (R & 1) + h];
-      }
+      for (int rb = 0; rb < WM; ++rb)
+        af[rb] = __uint_as_float(__float_as_uint(xf[2 * j + xoff[rb]]) ^ xneg[rb]);
 #pragma unroll
-      for (int cb = 0; cb < WN; ++cb) {
+      for (int cb = 0; cb < WN; ++cb)
         bf[cb] = reinterpret_cast<const float*>(&Bs[buf][j][0])[2 * ((wn * WN + cb) * 32 + l32) + h];
-      }
 #pragma unroll
       for (int rb = 0; rb < WM; ++rb)
 #pragma unroll
         for (int cb = 0; cb < WN; ++cb)
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[rb], bf[cb], acc[rb][cb], 0, 0, 0);
     }
-    if (ks + 1 < nsteps_eff) produce(ks + 1, buf ^ 1);
+  };
+
+  if (ns > 0) {
+    Stager<NT, XW, KS> stg;
+    stg.load(a.v, tl.cbase, tl.tau0, tl.yend, hptr(0), tid);
+    stg.store(&Xh[0][0], &Xy[0][0], tid);
+    const float2 h0 = stg.hv;
+    stg.load(a.v, tl.cbase + KS, tl.tau0, tl.yend, hptr(1), tid);
+    stg.store(&Xh[1][0], &Xy[1][0], tid);
+    float2 hnext = stg.hv;
     __syncthreads();
+    produce(0, h0);
+    __syncthreads();
+    int xb = 0;  // = ks % 3
+    for (int ks = 0; ks + 1 < ns; ++ks) {
+      const int buf = ks & 1;
+      const int xb2 = xb == 0 ? 2 : xb - 1;  // (ks + 2) % 3
+      stg.load(a.v, tl.cbase + (int64_t)(ks + 2) * KS, tl.tau0, tl.yend, hptr(ks + 2), tid);
+      mfma_step(xb, buf);
+      produce(buf ^ 1, hnext);
+      stg.store(&Xh[xb2][0], &Xy[buf][0], tid);
+      hnext = stg.hv;
+      xb = xb == 2 ? 0 : xb + 1;
+      __syncthreads();
+    }
+    mfma_step(xb, (ns - 1) & 1);
   }
-  store_tiles<WM, WN, AW>(a, id, tau0, alpha0, wm, wn, lane, acc);
+  store_tiles<WM, WN, AW>(a, tl.id, tl.tau0, tl.alpha0, wm, wn, lane, acc);
 }
 
 // ----------------------------------------------------------------------------- BF16/FP16 contraction
@@ -233,9 +325,14 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_f32(Contra
 // v_mfma_f32_32x32x16_{bf16,f16}: a lane holds A'[row = lane%32][8*(lane/32) + s]
 // and B'[8*(lane/32) + s][col = lane%32], s = 0..7, i.e. four consecutive complex
 // samples (re, im interleaved) starting at sample 4*(lane/32) of the 8-sample
-// K block.  The Hankel operand is staged as four copies shifted by 0..3 samples
-// so every 16-byte fragment read is aligned whatever the lag.
-template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS>
+// K block.  The Hankel operand is kept as eight copies (cr, sh) holding the
+// pairs (re, -im) (cr = 0) or (im, re) (cr = 1) of the window shifted by
+// sh = 0..3 samples, so every 16-byte fragment read is aligned for any lag.
+// Copy (cr, sh) starts at word cr*CO + sh*ZP with ZP = 8 and CO = 4 (mod 32):
+// the eight copies that a group of eight lanes reads at one offset, and the
+// eight 16-byte blocks that eight lanes write while staging, fall on disjoint
+// banks.
+template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS, int SCHED>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_16(ContractArgs a) {
   using O = Op<PREC>;
   constexpr int NT = 64 * WAVES_M * WAVES_N;
@@ -245,67 +342,75 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_16(Contrac
   static_assert(KS % 8 == 0 && TW % 16 == 0, "shape");
   constexpr int G = KS * AW / NT;
   static_assert(G >= 4 && G * NT == KS * AW && KS % G == 0 && G % 4 == 0, "B-gen split");
-  constexpr int ZW = KS + TW;          // entries per shifted copy (multiple of 4)
-  constexpr int ZU = 2 * 4 * (ZW / 4); // staging units of 4 entries
-  constexpr int BP = KS + 4;           // B row pitch (uint32), keeps rows 16-byte aligned
+  constexpr int ZW = KS + TW;                    // entries per shifted copy (multiple of 4)
+  constexpr int ZP = ((ZW + 31) / 32) * 32 + 8;  // copy pitch, = 8 (mod 32)
+  constexpr int CO = 4 * ZP + 4;                 // offset of the cr = 1 copies, = 4 (mod 32)
+  constexpr int ZS = CO + 4 * ZP;                // words per buffer
+  constexpr int XW = ZW + 4;                     // staged Hankel samples (ZW + 3 are read)
+  constexpr int BP = KS + 4;                     // B row pitch (uint32), rows 16-byte aligned
   constexpr int NB = SPLIT ? 2 : 1;
+  constexpr int ZU = ZW;                         // staging units: 4 entries x 1 shift x both cr
+  constexpr int ZR = (ZU + NT - 1) / NT;
 
-  __shared__ __attribute__((aligned(16))) uint32_t Zs[2][2][4][ZW];
+  __shared__ __attribute__((aligned(16))) uint32_t Zs[2][ZS];
   __shared__ __attribute__((aligned(16))) uint32_t Bs[2][NB][NC][BP];
+  __shared__ __attribute__((aligned(16))) float2 Xh[2][XW];
+  __shared__ __attribute__((aligned(16))) float2 Xy[2][KS];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
   const int h = lane >> 5, l32 = lane & 31;
-  const TileId id = tile_of(a);
-  const int tau0 = id.tt * TW, alpha0 = id.at * AW;
-  const int64_t cbase = a.v_off + (int64_t)id.chunk * a.Kc;
-  const int64_t mprod = min((int64_t)a.Kc, a.n_prod - (int64_t)id.chunk * a.Kc);
-  const int nsteps = a.Kc / KS;
-  const int nsteps_eff = (int)((mprod + KS - 1) / KS);
+  const Tile tl(a, TW, AW, KS);
+  const int ns = tl.ns;
 
   const int ga = tid % AW, gj = (tid / AW) * G;
-  const int galpha = alpha0 + ga;
+  const int galpha = tl.alpha0 + ga;
   const bool aval = galpha < a.A;
   float2 lo[G];
 #pragma unroll
   for (int g = 0; g < G; ++g)
     lo[g] = aval ? a.Lo[(int64_t)galpha * KS + gj + g] : make_float2(0.f, 0.f);
-  const float2* Hrow = a.H + (int64_t)(aval ? galpha : 0) * nsteps;
+  const float2* Hrow = a.H + (int64_t)(aval ? galpha : 0) * tl.nsteps;
+  auto hptr = [&](int ks) { return Hrow + min(ks, tl.nsteps - 1); };
 
-  auto produce = [&](int ks, int buf) {
-    const int64_t s0 = cbase + (int64_t)ks * KS;
-    // Hankel operand: copy (cr, sh) entry i holds the pair for sample s0+tau0+i+sh,
-    // cr = 0: (re, -im), cr = 1: (im, re).
-    for (int u = tid; u < ZU; u += NT) {
-      const int grp = u % (ZW / 4);
-      const int sh = (u / (ZW / 4)) & 3;
-      const int cr = u / ZW;
-      const int64_t g0 = s0 + tau0 + 4 * grp + sh;
-      uint32_t w[4];
+  int zoff[WM];
+#pragma unroll
+  for (int rb = 0; rb < WM; ++rb) {
+    const int R = (wm * WM + rb) * 32 + l32;
+    const int p0 = (R >> 1) + 4 * h;
+    const int sh = p0 & 3;
+    zoff[rb] = (R & 1) * CO + sh * ZP + (p0 - sh);
+  }
+
+  auto produce = [&](int buf, float2 hv) {
+    // Hankel copies from the FP32 window; unit u -> (grp = u/4, sh = u%4), units
+    // past ZU repeat earlier ones (identical values to identical addresses).
+#pragma unroll
+    for (int i = 0; i < ZR; ++i) {
+      const int u = (tid + i * NT) % ZU;
+      const int grp = u >> 2, sh = u & 3;
+      uint32_t w0[4], w1[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const float2 v = vload(a.v, g0 + k);
-        w[k] = cr ? O::pack(v.y, v.x) : O::pack(v.x, -v.y);
+        const float2 v = Xh[buf][4 * grp + sh + k];
+        w0[k] = O::pack(v.x, -v.y);
+        w1[k] = O::pack(v.y, v.x);
       }
-      *reinterpret_cast<uint4*>(&Zs[buf][cr][sh][4 * grp]) = make_uint4(w[0], w[1], w[2], w[3]);
+      *reinterpret_cast<uint4*>(&Zs[buf][sh * ZP + 4 * grp]) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
+      *reinterpret_cast<uint4*>(&Zs[buf][CO + sh * ZP + 4 * grp]) =
+          make_uint4(w1[0], w1[1], w1[2], w1[3]);
     }
-    // Modulated operands.
-    const float2 hv = aval ? Hrow[ks] : make_float2(0.f, 0.f);
+    // modulated operands
+    float2 y[G], yc[G];
+    modulate<G>(&Xy[buf][gj], hv, lo, y, yc);
     uint32_t py[NB][G], pyc[NB][G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      const int j = gj + g;
-      const bool valid = aval && ((int64_t)ks * KS + j < mprod);
-      const float2 xv = vload(a.v, s0 + j);
-      const float2 w = cmul(hv, lo[g]);
-      float2 y = make_float2(xv.x * w.x + xv.y * w.y, xv.x * w.y - xv.y * w.x);
-      float2 yc = make_float2(xv.x * w.x - xv.y * w.y, xv.x * w.y + xv.y * w.x);
-      if (!valid) y = yc = make_float2(0.f, 0.f);
-      py[0][g] = O::pack(y.x, y.y);
-      pyc[0][g] = O::pack(yc.x, yc.y);
+      py[0][g] = O::pack(y[g].x, y[g].y);
+      pyc[0][g] = O::pack(yc[g].x, yc[g].y);
       if (SPLIT) {
-        py[NB - 1][g] = O::pack(y.x - O::rnd(y.x), y.y - O::rnd(y.y));
-        pyc[NB - 1][g] = O::pack(yc.x - O::rnd(yc.x), yc.y - O::rnd(yc.y));
+        py[NB - 1][g] = O::pack(y[g].x - O::rnd(y[g].x), y[g].y - O::rnd(y[g].y));
+        pyc[NB - 1][g] = O::pack(yc[g].x - O::rnd(yc[g].x), yc[g].y - O::rnd(yc[g].y));
       }
     }
 #pragma unroll
@@ -326,29 +431,14 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_16(Contrac
     for (int k = 0; k < WN; ++k)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][k][v] = 0.f;
-
-  // per-lane Hankel read offsets (fixed for the whole kernel)
-  int zoff[WM], zcr[WM], zsh[WM];
-#pragma unroll
-  for (int rb = 0; rb < WM; ++rb) {
-    const int R = (wm * WM + rb) * 32 + l32;
-    const int p0 = (R >> 1) + 4 * h;
-    zcr[rb] = R & 1;
-    zsh[rb] = p0 & 3;
-    zoff[rb] = p0 - zsh[rb];
-  }
-
-  if (nsteps_eff > 0) produce(0, 0);
-  __syncthreads();
-  for (int ks = 0; ks < nsteps_eff; ++ks) {
-    const int buf = ks & 1;
+  auto mfma_step = [&](int buf) {
+    const uint32_t* zb = &Zs[buf][0];
 #pragma unroll
     for (int kb = 0; kb < KS / 8; ++kb) {
       const int j0 = kb * 8;
       uint4 af[WM], bf[NB][WN];
 #pragma unroll
-      for (int rb = 0; rb < WM; ++rb)
-        af[rb] = *reinterpret_cast<const uint4*>(&Zs[buf][zcr[rb]][zsh[rb]][zoff[rb] + j0]);
+      for (int rb = 0; rb < WM; ++rb) af[rb] = *reinterpret_cast<const uint4*>(zb + zoff[rb] + j0);
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -363,10 +453,42 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_16(Contrac
           if (SPLIT) acc[rb][cb] = O::mfma(af[rb], bf[NB - 1][cb], acc[rb][cb]);
         }
     }
-    if (ks + 1 < nsteps_eff) produce(ks + 1, buf ^ 1);
+  };
+
+  if (ns > 0) {
+    Stager<NT, XW, KS> stg;
+    stg.load(a.v, tl.cbase, tl.tau0, tl.yend, hptr(0), tid);
+    stg.store(&Xh[0][0], &Xy[0][0], tid);
+    const float2 h0 = stg.hv;
+    stg.load(a.v, tl.cbase + KS, tl.tau0, tl.yend, hptr(1), tid);
+    stg.store(&Xh[1][0], &Xy[1][0], tid);
+    float2 hnext = stg.hv;
     __syncthreads();
+    produce(0, h0);
+    __syncthreads();
+    for (int ks = 0; ks + 1 < ns; ++ks) {
+      const int buf = ks & 1;
+      stg.load(a.v, tl.cbase + (int64_t)(ks + 2) * KS, tl.tau0, tl.yend, hptr(ks + 2), tid);
+      mfma_step(buf);
+      produce(buf ^ 1, hnext);
+      stg.store(&Xh[buf][0], &Xy[buf][0], tid);
+      hnext = stg.hv;
+      if (SCHED) {
+        // Interleave the next step's operand generation with this step's
+        // matrix-core instructions so one wave overlaps both.
+        constexpr int NMF = WM * WN * (KS / 8) * NB;
+#pragma unroll
+        for (int i = 0; i < NMF; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+          __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // VALU
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
+        }
+      }
+      __syncthreads();
+    }
+    mfma_step((ns - 1) & 1);
   }
-  store_tiles<WM, WN, AW>(a, id, tau0, alpha0, wm, wn, lane, acc);
+  store_tiles<WM, WN, AW>(a, tl.id, tl.tau0, tl.alpha0, wm, wn, lane, acc);
 }
 
 // ----------------------------------------------------------------------------- config table
@@ -378,9 +500,9 @@ hipError_t launch_f32(const ContractArgs& a, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS>
+template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS, int SCHED>
 hipError_t launch_16(const ContractArgs& a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((contract_16<PREC, SPLIT, TW, AW, WAVES_M, WAVES_N, KS>), dim3(grid),
+  hipLaunchKernelGGL((contract_16<PREC, SPLIT, TW, AW, WAVES_M, WAVES_N, KS, SCHED>), dim3(grid),
                      dim3(64 * WAVES_M * WAVES_N), 0, st, a);
   return hipGetLastError();
 }
@@ -388,24 +510,28 @@ hipError_t launch_16(const ContractArgs& a, int grid, hipStream_t st) {
 #define CFG_F32(TW, AW, WMW, WNW, KS)                                                       \
   {PREC_F32, 0, TW, AW, KS, 64 * WMW * WNW, &launch_f32<TW, AW, WMW, WNW, KS>,              \
    "f32_t" #TW "_a" #AW "_w" #WMW "x" #WNW "_k" #KS}
-#define CFG_16(P, PN, SP, TW, AW, WMW, WNW, KS)                                             \
-  {P, SP, TW, AW, KS, 64 * WMW * WNW, &launch_16<P, SP, TW, AW, WMW, WNW, KS>,              \
-   PN "_s" #SP "_t" #TW "_a" #AW "_w" #WMW "x" #WNW "_k" #KS}
-#define CFG_16_ALL(TW, AW, WMW, WNW, KS)                \
-  CFG_16(PREC_BF16, "bf16", 0, TW, AW, WMW, WNW, KS),   \
-  CFG_16(PREC_BF16, "bf16", 1, TW, AW, WMW, WNW, KS),   \
-  CFG_16(PREC_F16, "f16", 0, TW, AW, WMW, WNW, KS),     \
-  CFG_16(PREC_F16, "f16", 1, TW, AW, WMW, WNW, KS)
+#define CFG_16(P, PN, SP, TW, AW, WMW, WNW, KS, SC)                                         \
+  {P, SP, TW, AW, KS, 64 * WMW * WNW, &launch_16<P, SP, TW, AW, WMW, WNW, KS, SC>,          \
+   PN "_s" #SP "_t" #TW "_a" #AW "_w" #WMW "x" #WNW "_k" #KS "_i" #SC}
+#define CFG_16_ALL(TW, AW, WMW, WNW, KS, SC)                \
+  CFG_16(PREC_BF16, "bf16", 0, TW, AW, WMW, WNW, KS, SC),   \
+  CFG_16(PREC_BF16, "bf16", 1, TW, AW, WMW, WNW, KS, SC),   \
+  CFG_16(PREC_F16, "f16", 0, TW, AW, WMW, WNW, KS, SC),     \
+  CFG_16(PREC_F16, "f16", 1, TW, AW, WMW, WNW, KS, SC)
 
+// The first configuration of each (precision, split, lag tile) is the default.
 static const KernelCfg g_cfgs[] = {
     CFG_F32(128, 64, 4, 1, 16),
     CFG_F32(64, 64, 2, 1, 16),
     CFG_F32(32, 64, 1, 2, 16),
     CFG_F32(64, 128, 2, 2, 16),
-    CFG_16_ALL(128, 64, 4, 1, 32),
-    CFG_16_ALL(64, 64, 2, 1, 32),
-    CFG_16_ALL(32, 64, 1, 2, 32),
-    CFG_16_ALL(64, 128, 2, 2, 32),
+    CFG_16_ALL(128, 64, 4, 1, 32, 0),
+    CFG_16_ALL(64, 64, 2, 1, 32, 0),
+    CFG_16_ALL(32, 64, 1, 2, 32, 0),
+    CFG_16_ALL(64, 128, 2, 2, 32, 0),
+    CFG_16_ALL(128, 64, 4, 1, 32, 1),
+    CFG_16_ALL(128, 128, 4, 2, 32, 0),
+    CFG_16_ALL(128, 128, 4, 2, 32, 1),
 };
 
 const KernelCfg* kernel_cfgs(int* n) {
@@ -497,6 +623,22 @@ __global__ void finalize_kernel(const double2* S, int hasS, const float2* part0,
 __global__ void vcopy_kernel(VSrc v, int64_t shift, int64_t n, float2* dst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = vload(v, shift + i);
+}
+
+// Deterministic unit-magnitude test samples for the autotuner's timing runs.
+__global__ void pattern_kernel(float2* x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    float s, c;
+    __sincosf(0.001f * (float)(i % 100003) + 0.3f * (float)(i % 7), &s, &c);
+    x[i] = make_float2(c, s);
+  }
+}
+
+hipError_t launch_pattern(float2* x, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pattern_kernel, dim3((int)((n + 255) / 256)), dim3(256), 0, st, x, n);
+  return hipGetLastError();
 }
 
 __global__ void zero_kernel(uint32_t* p, int64_t nwords) {

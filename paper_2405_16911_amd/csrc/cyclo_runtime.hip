@@ -17,7 +17,12 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <cstdio>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/cyclo.h"
@@ -63,14 +68,82 @@ int64_t env_i64(const char* name, int64_t dflt) {
   return (end && *end == 0) ? (int64_t)r : dflt;
 }
 
-// Chooses the contraction kernel for (precision, split, T, A).  CYC_KERNEL_CFG
-// overrides with an index into the configuration table when it matches.
-int pick_cfg(int prec, int split, int T) {
+// ---- tuning cache: (arch, prec, split, T, A-bucket) -> configuration name
+typedef std::tuple<std::string, int, int, int, int> TuneKey;
+std::mutex g_tune_mu;
+std::map<TuneKey, std::string> g_tune;
+bool g_tune_loaded = false;
+
+int a_bucket(int A) {
+  int b = 0;
+  while ((1 << b) < A && b < 30) ++b;
+  return b;
+}
+
+std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t colon = a.find(':');
+  return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+int cfg_by_name(const std::string& name) {
+  int n = 0;
+  const KernelCfg* c = kernel_cfgs(&n);
+  for (int i = 0; i < n; ++i)
+    if (name == c[i].name) return i;
+  return -1;
+}
+
+// Cache file format, one entry per line: "arch prec split T abucket cfg_name".
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("CYC_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char arch[64], name[128];
+  int prec, split, T, ab;
+  while (std::fscanf(f, "%63s %d %d %d %d %127s", arch, &prec, &split, &T, &ab, name) == 6)
+    g_tune[TuneKey(arch, prec, split, T, ab)] = name;
+  std::fclose(f);
+}
+
+void tune_store(const TuneKey& k, const std::string& name) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  g_tune[k] = name;
+  const char* path = std::getenv("CYC_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d %d %d %s\n", std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k),
+               std::get<3>(k), std::get<4>(k), name.c_str());
+  std::fclose(f);
+}
+
+// Chooses the contraction kernel for (precision, split, T, A): an explicit
+// CYC_KERNEL_CFG index if it implements the mode, else the tuning cache, else
+// the first configuration whose lag tile fits T.
+int pick_cfg(int prec, int split, int T, int A) {
   int n = 0;
   const KernelCfg* c = kernel_cfgs(&n);
   const int64_t forced = env_i64("CYC_KERNEL_CFG", -1);
   if (forced >= 0 && forced < n && c[forced].prec == prec && c[forced].split == split)
     return (int)forced;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(TuneKey(device_arch(), prec, split, T, a_bucket(A)));
+    if (it != g_tune.end()) {
+      const int i = cfg_by_name(it->second);
+      if (i >= 0 && c[i].prec == prec && c[i].split == split) return i;
+    }
+  }
   const int want_tw = T > 64 ? 128 : (T > 32 ? 64 : 32);
   for (int i = 0; i < n; ++i)
     if (c[i].prec == prec && c[i].split == split && c[i].tw == want_tw && c[i].aw == 64) return i;
@@ -171,7 +244,7 @@ int cyc_create(cyc_state** out, const double* alphas_host, int32_t n_alpha, int3
   s->T = n_lag;
   s->A = n_alpha;
   s->flags = flags;
-  s->cfg = pick_cfg(prec, split, n_lag);
+  s->cfg = pick_cfg(prec, split, n_lag, n_alpha);
   if (s->cfg < 0) {
     delete s;
     return CYC_EUNSUPPORTED;
@@ -342,6 +415,93 @@ int cyc_profile_read(cyc_state* s, double* total_ms, int64_t* launches, double* 
   if (total_ms) *total_ms = ms;
   if (launches) *launches = (int64_t)(s->ev_used / 2);
   if (work) *work = s->prof_work;
+  return CYC_OK;
+}
+
+int cyc_kernel_cfg_count(void) {
+  int n = 0;
+  kernel_cfgs(&n);
+  return n;
+}
+
+int cyc_kernel_cfg_info(int32_t idx, uint32_t* flags, int32_t* lag_tile, int32_t* alpha_tile,
+                        int32_t* threads, const char** name) {
+  int n = 0;
+  const KernelCfg* c = kernel_cfgs(&n);
+  if (idx < 0 || idx >= n) return CYC_EINVAL;
+  if (flags) *flags = (uint32_t)c[idx].prec | (c[idx].split ? CYC_TW_SPLIT : 0u);
+  if (lag_tile) *lag_tile = c[idx].tw;
+  if (alpha_tile) *alpha_tile = c[idx].aw;
+  if (threads) *threads = c[idx].nthreads;
+  if (name) *name = c[idx].name;
+  return CYC_OK;
+}
+
+int cyc_set_kernel_cfg(cyc_state* s, int32_t idx) {
+  int n = 0;
+  const KernelCfg* c = kernel_cfgs(&n);
+  if (!s || idx < 0 || idx >= n) return CYC_EINVAL;
+  const KernelCfg& cur = c[s->cfg];
+  if (c[idx].prec != cur.prec || c[idx].split != cur.split || c[idx].ks != cur.ks)
+    return CYC_EUNSUPPORTED;
+  s->cfg = idx;
+  return CYC_OK;
+}
+
+int cyc_autotune(int32_t n_alpha, int32_t n_lag, uint32_t flags, int32_t* best_cfg, double* best_ms,
+                 void* stream) {
+  if (n_alpha < 1 || n_lag < 1 || n_lag > kMaxLag) return CYC_EINVAL;
+  hipStream_t st = as_stream(stream);
+  // synthetic alphas (uniform grid) and samples (a fixed non-trivial pattern)
+  std::vector<double> al(n_alpha);
+  for (int i = 0; i < n_alpha; ++i) al[i] = -0.5 + (double)i / n_alpha;
+  cyc_state* s = nullptr;
+  int rc = cyc_create(&s, al.data(), n_alpha, n_lag, flags & ~CYC_OUT_C128, stream);
+  if (rc != CYC_OK) return rc;
+  const int64_t nsamp = (int64_t)s->Kc * 16 + n_lag - 1;
+  float2* x = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipMalloc(reinterpret_cast<void**>(&x), sizeof(float2) * nsamp) != hipSuccess) {
+    cyc_destroy(s);
+    return CYC_ENOMEM;
+  }
+  rc = CYC_OK;
+  if (launch_pattern(x, nsamp, st) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess)
+    rc = CYC_EDEVICE;
+  int n = 0;
+  const KernelCfg* c = kernel_cfgs(&n);
+  const int prec = (int)(flags & CYC_OP_MASK), split = (flags & CYC_TW_SPLIT) ? 1 : 0;
+  int best = -1;
+  double bms = 1e300;
+  for (int i = 0; i < n && rc == CYC_OK; ++i) {
+    if (c[i].prec != prec || c[i].split != split || cyc_set_kernel_cfg(s, i) != CYC_OK) continue;
+    double ms_min = 1e300;
+    for (int rep = 0; rep < 4 && rc == CYC_OK; ++rep) {
+      cyc_reset(s);
+      float t = 0.f;
+      if (hipEventRecord(e0, st) != hipSuccess || cyc_push(s, x, nsamp, stream) != CYC_OK ||
+          hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+        rc = CYC_EDEVICE;
+        break;
+      }
+      if (rep > 0) ms_min = std::min(ms_min, (double)t);
+    }
+    if (rc == CYC_OK && ms_min < bms) {
+      bms = ms_min;
+      best = i;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(x);
+  cyc_destroy(s);
+  if (rc != CYC_OK) return rc;
+  if (best < 0) return CYC_EUNSUPPORTED;
+  tune_store(TuneKey(device_arch(), prec, split, n_lag, a_bucket(n_alpha)), c[best].name);
+  if (best_cfg) *best_cfg = best;
+  if (best_ms) *best_ms = bms;
   return CYC_OK;
 }
 

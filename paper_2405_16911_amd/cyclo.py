@@ -41,6 +41,14 @@ SIGNATURES = {
     "cyc_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.c_int32)]),
+    "cyc_kernel_cfg_count": (ctypes.c_int, []),
+    "cyc_kernel_cfg_info": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32),
+                                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_char_p)]),
+    "cyc_set_kernel_cfg": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "cyc_autotune": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
+                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.c_void_p]),
     "cyc_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "cyc_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
@@ -148,6 +156,30 @@ def cyc_profile_read(state) -> dict:
     return dict(total_ms=ms.value, launches=n.value, work=w.value)
 
 
+def cyc_kernel_cfg_count() -> int:
+    return int(lib().cyc_kernel_cfg_count())
+
+
+def cyc_kernel_cfg_info(idx: int) -> dict:
+    fl, tw, aw, nt = ctypes.c_uint32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    name = ctypes.c_char_p()
+    _check(lib().cyc_kernel_cfg_info(int(idx), ctypes.byref(fl), ctypes.byref(tw), ctypes.byref(aw),
+                                     ctypes.byref(nt), ctypes.byref(name)), "cyc_kernel_cfg_info")
+    return dict(index=int(idx), flags=fl.value, lag_tile=tw.value, alpha_tile=aw.value,
+                threads=nt.value, name=name.value.decode())
+
+
+def cyc_set_kernel_cfg(state, idx: int):
+    _check(lib().cyc_set_kernel_cfg(state, int(idx)), "cyc_set_kernel_cfg")
+
+
+def cyc_autotune(n_alpha: int, n_lag: int, flags: int = 0, stream=None) -> dict:
+    best, ms = ctypes.c_int32(-1), ctypes.c_double(0.0)
+    _check(lib().cyc_autotune(int(n_alpha), int(n_lag), int(flags), ctypes.byref(best), ctypes.byref(ms),
+                              _stream_handle(stream)), "cyc_autotune")
+    return dict(cfg=best.value, ms_per_push=ms.value, name=cyc_kernel_cfg_info(best.value)["name"])
+
+
 # ----------------------------------------------------------------------------- convenience wrapper
 
 class CyclicStream:
@@ -177,6 +209,9 @@ class CyclicStream:
 
     def query(self) -> dict:
         return cyc_query(self._s)
+
+    def set_kernel_cfg(self, idx: int):
+        cyc_set_kernel_cfg(self._s, idx)
 
     def profile(self, enable: bool):
         cyc_profile(self._s, enable)

@@ -73,3 +73,21 @@ def test_invalid_arguments_rejected_on_host(L):
     assert L.cyc_profile(None, 1) == cyclo.CYC_EINVAL
     assert L.cyc_profile_read(None, None, None, None) == cyclo.CYC_EINVAL
     L.cyc_destroy(None)
+
+
+def test_kernel_configurations_enumerate(L):
+    n = cyclo.cyc_kernel_cfg_count()
+    assert n > 0
+    infos = [cyclo.cyc_kernel_cfg_info(i) for i in range(n)]
+    names = [i["name"] for i in infos]
+    assert len(set(names)) == n
+    modes = {(i["flags"]) for i in infos}
+    # every precision / split mode the ABI accepts has at least one configuration
+    assert {0x0, 0x1, 0x2, 0x1 | 0x4, 0x2 | 0x4} <= modes
+    for i in infos:
+        assert i["lag_tile"] % 16 == 0 and i["alpha_tile"] > 0 and i["threads"] % 64 == 0
+    with pytest.raises(cyclo.CycloError):
+        cyclo.cyc_kernel_cfg_info(n)
+    assert L.cyc_kernel_cfg_info(-1, None, None, None, None, None) == cyclo.CYC_EINVAL
+    assert L.cyc_set_kernel_cfg(None, 0) == cyclo.CYC_EINVAL
+    assert L.cyc_autotune(0, 4, 0, None, None, None) == cyclo.CYC_EINVAL

@@ -103,6 +103,50 @@ def test_ragged_shapes(cy, flags, T, A):
     R, Rc, n, q = _run(cy, x, alphas, T, flags=flags, splits=[1000, 5000, 1, 7000, L - 13001])
     assert q["n_committed"] == ((L - T + 1) // q["chunk"]) * q["chunk"]
     _check(x, alphas, T, R, Rc, n, TOL[flags & 3])
+    # run-to-run bitwise reproducibility (fixed reduction order, no races)
+    R2, Rc2, _, _ = _run(cy, x, alphas, T, flags=flags)
+    assert np.array_equal(R, R2) and np.array_equal(Rc, Rc2)
+
+
+def test_every_kernel_configuration(cy):
+    """Each tile configuration against the oracle; within one precision/split mode
+    all configurations give bit-identical tables (same operands, same order)."""
+    T, A = 70, 150
+    x = siggen.qpsk_rrc_stream(n=2 * 4096 + 555, seed=9)
+    alphas = np.random.default_rng(1).uniform(-0.5, 0.5, size=A)
+    by_mode = {}
+    for idx in range(cy.cyc_kernel_cfg_count()):
+        info = cy.cyc_kernel_cfg_info(idx)
+        st = cy.CyclicStream(alphas, T, info["flags"])
+        st.set_kernel_cfg(idx)
+        xd = _dev(x)
+        st.push(xd[:5000])
+        st.push(xd[5000:])
+        R, Rc, n = st.read()
+        torch.cuda.synchronize()
+        st.close()
+        R, Rc = R.cpu().numpy(), Rc.cpu().numpy()
+        print(f"  cfg {idx} {info['name']}", flush=True)
+        _check(x, alphas, T, R, Rc, n, TOL[info["flags"] & 3])
+        ref = by_mode.setdefault(info["flags"], (R, Rc))
+        assert np.array_equal(ref[0], R) and np.array_equal(ref[1], Rc), info["name"]
+
+
+def test_autotune_picks_a_configuration(cy, tmp_path):
+    cache = tmp_path / "tune.txt"
+    os.environ["CYC_TUNE_CACHE"] = str(cache)
+    try:
+        res = cy.cyc_autotune(300, 40, cy.CYC_OP_BF16)
+        assert res["cfg"] >= 0 and res["ms_per_push"] > 0
+        info = cy.cyc_kernel_cfg_info(res["cfg"])
+        assert info["flags"] == cy.CYC_OP_BF16
+        st = cy.CyclicStream(np.arange(300) / 300, 40, cy.CYC_OP_BF16)
+        assert st.query()["kernel_cfg"] == res["cfg"]
+        st.close()
+        line = cache.read_text().split()
+        assert line[-1] == info["name"] and line[3] == "40"
+    finally:
+        os.environ.pop("CYC_TUNE_CACHE", None)
 
 
 def test_segmentation_bitwise_and_determinism(cy):
