@@ -39,8 +39,11 @@ __device__ __forceinline__ float2 vload(const VSrc& v, int64_t g) {
   return *p;
 }
 
+// Complex product with explicit FMAs, so every kernel that generates operands
+// rounds them identically.
 __device__ __forceinline__ float2 cmul(float2 p, float2 q) {
-  return make_float2(p.x * q.x - p.y * q.y, p.x * q.y + p.y * q.x);
+  const float t1 = p.y * q.y, t2 = p.y * q.x;
+  return make_float2(__fmaf_rn(p.x, q.x, -t1), __fmaf_rn(p.x, q.y, t2));
 }
 
 // frac(alpha * n) in [0, 1): error-free product p + e = alpha*n (FMA), then
@@ -78,13 +81,21 @@ template <>
 struct Op<PREC_F16> {
   typedef _Float16 e2 __attribute__((ext_vector_type(2)));
   typedef _Float16 e8 __attribute__((ext_vector_type(8)));
+  // The empty asm makes each input an FP32 register value first, so the
+  // conversion is always FP32 -> FP16 round-to-nearest and is never fused with
+  // the FMA that produced the value (a fused form rounds once and differs in
+  // the last bit, which would make kernels disagree with each other).
   static __device__ __forceinline__ uint32_t pack(float a, float b) {
+    asm volatile("" : "+v"(a), "+v"(b));
     e2 v;
     v.x = (_Float16)a;
     v.y = (_Float16)b;
     return __builtin_bit_cast(uint32_t, v);
   }
-  static __device__ __forceinline__ float rnd(float a) { return (float)(_Float16)a; }
+  static __device__ __forceinline__ float rnd(float a) {
+    asm volatile("" : "+v"(a));
+    return (float)(_Float16)a;
+  }
   static __device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(e8, a),
                                                  __builtin_bit_cast(e8, b), c, 0, 0, 0);
@@ -491,6 +502,226 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_16(Contrac
   store_tiles<WM, WN, AW>(a, tl.id, tl.tau0, tl.alpha0, wm, wn, lane, acc);
 }
 
+// ----------------------------------------------------------------------------- register-B contraction
+//
+// BF16/FP16 variant for large lag tiles.  One wave per workgroup owns every
+// row of the tile (RB blocks of 32 rows = 16 lags each) and NA blocks of 32
+// cycle frequencies.  The modulated operands are generated directly in the
+// registers of the matrix-core B fragment (lane = alpha, four consecutive
+// samples per lane half), so they never pass through LDS; LDS holds only the
+// FP32 sample window and the eight shifted Hankel copies, double-buffered.
+// Accumulators: RB x 2NA blocks (Y blocks first, then Yc blocks).
+template <int PREC, int SPLIT, int RB, int NA, int KS>
+__global__ __launch_bounds__(64, 1) void contract_rg(ContractArgs a) {
+  using O = Op<PREC>;
+  constexpr int NT = 64;
+  constexpr int TW = 16 * RB, AW = 32 * NA;
+  static_assert(KS % 8 == 0, "shape");
+  constexpr int NKB = KS / 8;                    // 8-sample K blocks per step
+  constexpr int ZW = KS + TW;
+  constexpr int ZP = ((ZW + 31) / 32) * 32 + 8;  // see contract_16
+  constexpr int CO = 4 * ZP + 4;
+  constexpr int ZS = CO + 4 * ZP;
+  constexpr int XW = ZW + 4;
+  constexpr int ZU = ZW;
+  constexpr int ZR = (ZU + NT - 1) / NT;
+  constexpr int NB = SPLIT ? 2 : 1;
+
+  __shared__ __attribute__((aligned(16))) uint32_t Zs[2][ZS];
+  __shared__ __attribute__((aligned(16))) float2 Xh[3][XW];
+  __shared__ __attribute__((aligned(16))) float2 Xy[3][KS];
+
+  const int tid = threadIdx.x, lane = tid;
+  const int h = lane >> 5, l32 = lane & 31;
+  const Tile tl(a, TW, AW, KS);
+  const int ns = tl.ns;
+
+  // lane's cycle frequencies and the chunk-relative twiddles of the samples it
+  // generates: j = 8 kb + 4 h + g within a step
+  float2 lo[NA][NKB][4];
+  const float2* Hrow[NA];
+#pragma unroll
+  for (int nb = 0; nb < NA; ++nb) {
+    const int al = tl.alpha0 + nb * 32 + l32;
+    const bool ok = al < a.A;
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        lo[nb][kb][g] = ok ? a.Lo[(int64_t)al * KS + 8 * kb + 4 * h + g] : make_float2(0.f, 0.f);
+    Hrow[nb] = a.H + (int64_t)(ok ? al : 0) * tl.nsteps;
+  }
+  auto hidx = [&](int ks) { return min(ks, tl.nsteps - 1); };
+
+  int zoff[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const int R = rb * 32 + l32;
+    const int p0 = (R >> 1) + 4 * h;
+    const int sh = p0 & 3;
+    zoff[rb] = (R & 1) * CO + sh * ZP + (p0 - sh);
+  }
+
+  auto build_hankel = [&](int xbuf, int buf) {
+#pragma unroll
+    for (int i = 0; i < ZR; ++i) {
+      const int u = (tid + i * NT) % ZU;
+      const int grp = u >> 2, sh = u & 3;
+      uint32_t w0[4], w1[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float2 v = Xh[xbuf][4 * grp + sh + k];
+        w0[k] = O::pack(v.x, -v.y);
+        w1[k] = O::pack(v.y, v.x);
+      }
+      *reinterpret_cast<uint4*>(&Zs[buf][sh * ZP + 4 * grp]) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
+      *reinterpret_cast<uint4*>(&Zs[buf][CO + sh * ZP + 4 * grp]) =
+          make_uint4(w1[0], w1[1], w1[2], w1[3]);
+    }
+  };
+
+  f32x16 acc[RB][2 * NA];
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int k = 0; k < 2 * NA; ++k)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][k][v] = 0.f;
+
+  // Operands of one 8-sample K block: Hankel fragments from LDS, modulated
+  // fragments generated in registers from samples already held in registers.
+  struct Frag {
+    uint4 a[RB];
+    uint4 y[NB][NA], yc[NB][NA];
+  };
+  typedef float2 StepX[NKB][4];  // this lane's samples of one step: j = 8 kb + 4 h + g
+  auto load_x = [&](int xbuf, StepX& xs) {
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+      const float4 xa = *reinterpret_cast<const float4*>(&Xy[xbuf][8 * kb + 4 * h]);
+      const float4 xb = *reinterpret_cast<const float4*>(&Xy[xbuf][8 * kb + 4 * h + 2]);
+      xs[kb][0] = make_float2(xa.x, xa.y);
+      xs[kb][1] = make_float2(xa.z, xa.w);
+      xs[kb][2] = make_float2(xb.x, xb.y);
+      xs[kb][3] = make_float2(xb.z, xb.w);
+    }
+  };
+  auto fetch = [&](int zbuf, int kb, const StepX& xs, const float2 (&hv)[NA], Frag& f) {
+    const uint32_t* zb = &Zs[zbuf][0];
+    const int j0 = kb * 8;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) f.a[rb] = *reinterpret_cast<const uint4*>(zb + zoff[rb] + j0);
+#pragma unroll
+    for (int nb = 0; nb < NA; ++nb) {
+      float2 y[4], yc[4];
+      modulate<4>(xs[kb], hv[nb], lo[nb][kb], y, yc);
+      uint32_t py[NB][4], pyc[NB][4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        py[0][g] = O::pack(y[g].x, y[g].y);
+        pyc[0][g] = O::pack(yc[g].x, yc[g].y);
+        if (SPLIT) {
+          py[NB - 1][g] = O::pack(y[g].x - O::rnd(y[g].x), y[g].y - O::rnd(y[g].y));
+          pyc[NB - 1][g] = O::pack(yc[g].x - O::rnd(yc[g].x), yc[g].y - O::rnd(yc[g].y));
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        f.y[b][nb] = make_uint4(py[b][0], py[b][1], py[b][2], py[b][3]);
+        f.yc[b][nb] = make_uint4(pyc[b][0], pyc[b][1], pyc[b][2], pyc[b][3]);
+      }
+    }
+  };
+  auto mma = [&](const Frag& f) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int nb = 0; nb < NA; ++nb)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          acc[rb][nb] = O::mfma(f.a[rb], f.y[b][nb], acc[rb][nb]);
+          acc[rb][NA + nb] = O::mfma(f.a[rb], f.yc[b][nb], acc[rb][NA + nb]);
+        }
+  };
+
+  // Software pipeline.  One wave per workgroup: its LDS operations execute in
+  // program order, so no barriers are needed, and a buffer is rewritten only
+  // after every read of it has been issued.  Sample windows are
+  // triple-buffered (Xh/Xy[ks % 3]) and their global loads land a full step
+  // before they are written to LDS; Hankel copies are double-buffered
+  // (Zs[ks & 1]) and built one step ahead; the step's samples for the
+  // modulated operands are read into registers one step ahead.
+  if (ns > 0) {
+    Stager<NT, XW, KS> stg;
+    float2 hc[NA], hn[NA], hnn[NA];
+    stg.load(a.v, tl.cbase, tl.tau0, tl.yend, Hrow[0] + hidx(0), tid);
+    stg.store(&Xh[0][0], &Xy[0][0], tid);
+    stg.load(a.v, tl.cbase + KS, tl.tau0, tl.yend, Hrow[0] + hidx(1), tid);
+    stg.store(&Xh[1][0], &Xy[1][0], tid);
+    stg.load(a.v, tl.cbase + 2 * KS, tl.tau0, tl.yend, Hrow[0] + hidx(2), tid);
+#pragma unroll
+    for (int nb = 0; nb < NA; ++nb) {
+      hc[nb] = Hrow[nb][hidx(0)];
+      hn[nb] = Hrow[nb][hidx(1)];
+      hnn[nb] = Hrow[nb][hidx(2)];
+    }
+    build_hankel(0, 0);
+    StepX xc, xn;
+    load_x(0, xc);
+    Frag cur;
+    fetch(0, 0, xc, hc, cur);
+    int w0 = 0;  // = ks % 3
+    for (int ks = 0; ks < ns; ++ks) {
+      const int w1 = w0 == 2 ? 0 : w0 + 1, w2 = w1 == 2 ? 0 : w1 + 1;
+      const int zb = ks & 1;
+      stg.store(&Xh[w2][0], &Xy[w2][0], tid);  // window of step ks+2 (loaded one step ago)
+      float2 h3[NA];
+#pragma unroll
+      for (int nb = 0; nb < NA; ++nb) h3[nb] = Hrow[nb][hidx(ks + 3)];
+      stg.load(a.v, tl.cbase + (int64_t)(ks + 3) * KS, tl.tau0, tl.yend, Hrow[0] + hidx(ks + 3), tid);
+      build_hankel(w1, zb ^ 1);  // Hankel copies of step ks+1
+      load_x(w1, xn);            // samples of step ks+1
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) {
+        Frag nxt;
+        if (kb + 1 < NKB)
+          fetch(zb, kb + 1, xc, hc, nxt);
+        else
+          fetch(zb ^ 1, 0, xn, hn, nxt);  // first block of step ks+1
+        mma(cur);
+        cur = nxt;
+      }
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) xc[kb][g] = xn[kb][g];
+#pragma unroll
+      for (int nb = 0; nb < NA; ++nb) {
+        hc[nb] = hn[nb];
+        hn[nb] = hnn[nb];
+        hnn[nb] = h3[nb];
+      }
+      w0 = w1;
+      {
+        constexpr int NMF = NKB * RB * 2 * NA * NB;
+#pragma unroll
+        for (int i = 0; i < NMF; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+          __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // VALU
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
+        }
+      }
+    }
+  }
+  store_tiles<RB, 2 * NA, AW>(a, tl.id, tl.tau0, tl.alpha0, 0, 0, lane, acc);
+}
+
+template <int PREC, int SPLIT, int RB, int NA, int KS>
+hipError_t launch_rg(const ContractArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((contract_rg<PREC, SPLIT, RB, NA, KS>), dim3(grid), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
 // ----------------------------------------------------------------------------- config table
 
 template <int TW, int AW, int WAVES_M, int WAVES_N, int KS>
@@ -519,6 +750,15 @@ hipError_t launch_16(const ContractArgs& a, int grid, hipStream_t st) {
   CFG_16(PREC_F16, "f16", 0, TW, AW, WMW, WNW, KS, SC),     \
   CFG_16(PREC_F16, "f16", 1, TW, AW, WMW, WNW, KS, SC)
 
+#define CFG_RG(P, PN, SP, RB, NA, KS)                                                      \
+  {P, SP, 16 * RB, 32 * NA, KS, 64, &launch_rg<P, SP, RB, NA, KS>,                           \
+   PN "_s" #SP "_t" #RB "x16_a" #NA "x32_reg_k" #KS}
+#define CFG_RG_ALL(RB, NA, KS)                  \
+  CFG_RG(PREC_BF16, "bf16", 0, RB, NA, KS),     \
+  CFG_RG(PREC_BF16, "bf16", 1, RB, NA, KS),     \
+  CFG_RG(PREC_F16, "f16", 0, RB, NA, KS),       \
+  CFG_RG(PREC_F16, "f16", 1, RB, NA, KS)
+
 // The first configuration of each (precision, split, lag tile) is the default.
 static const KernelCfg g_cfgs[] = {
     CFG_F32(128, 64, 4, 1, 16),
@@ -532,6 +772,8 @@ static const KernelCfg g_cfgs[] = {
     CFG_16_ALL(128, 64, 4, 1, 32, 1),
     CFG_16_ALL(128, 128, 4, 2, 32, 0),
     CFG_16_ALL(128, 128, 4, 2, 32, 1),
+    CFG_16_ALL(128, 128, 2, 2, 32, 1),
+    CFG_RG_ALL(8, 1, 32),
 };
 
 const KernelCfg* kernel_cfgs(int* n) {
