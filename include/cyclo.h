@@ -166,6 +166,47 @@ int cyc_set_kernel_cfg(cyc_state* s, int32_t idx);
 int cyc_autotune(int32_t n_alpha, int32_t n_lag, uint32_t flags, int32_t* best_cfg, double* best_ms,
                  void* stream);
 
+/*
+ * Batches: many independent stream states with a common lag count, each with
+ * its own cycle-frequency list, advanced together.  Per stream the semantics
+ * are exactly those of cyc_push / cyc_read (tables bit-identical to a single
+ * state fed the same samples with the same kernel configuration).  A push runs
+ * one persistent contraction launch over every committed chunk of every
+ * stream (work items taken from an atomic counter), bracketed by batched phase,
+ * accumulation and pending-sample kernels; the sequence is captured once in a
+ * HIP graph and replayed with new device-side descriptor tables (CYC_NO_GRAPH=1
+ * in the environment at cyc_batch_create launches the kernels directly instead).
+ *
+ * cyc_batch_create
+ *   n_streams     : number of streams, >= 1.
+ *   alpha_offsets : host array of n_streams+1 offsets into `alphas`
+ *                   (non-decreasing, alpha_offsets[0] = 0, each stream >= 1 alpha).
+ *   alphas        : host FP64 cycle frequencies of all streams, concatenated.
+ *   n_lag, flags  : as cyc_create (CYC_OP_*, CYC_TW_SPLIT, CYC_OUT_C128).
+ * cyc_batch_push
+ *   d_x : host array of n_streams device pointers (complex64 samples; a pointer
+ *         may be NULL when its count is 0); n : host array of n_streams counts.
+ *   The device buffers must stay unmodified until `stream` passes the call.
+ * cyc_batch_read
+ *   d_R, d_Rc : host arrays of n_streams device pointers to [T][A_s] tables
+ *               (either array, or any entry, may be NULL to skip).
+ *   n_used    : host array of n_streams (may be NULL).
+ * Errors: as the single-stream calls.  The batch allocates its descriptor
+ * tables and workspace at creation (CYC_WORKSPACE_MB bounds the partial-sum
+ * workspace; larger pushes are processed in several rounds).
+ */
+typedef struct cyc_batch cyc_batch;
+int cyc_batch_create(cyc_batch** out, int32_t n_streams, const int64_t* alpha_offsets,
+                     const double* alphas, int32_t n_lag, uint32_t flags, void* stream);
+int cyc_batch_push(cyc_batch* b, const void* const* d_x, const int64_t* n, void* stream);
+int cyc_batch_read(cyc_batch* b, void* const* d_R, void* const* d_Rc, int64_t* n_used,
+                   void* stream);
+int cyc_batch_reset(cyc_batch* b);
+void cyc_batch_destroy(cyc_batch* b);
+/* Kernel configuration in use, number of rounds of the last push and whether
+ * the last push replayed a captured graph (outputs may be NULL). */
+int cyc_batch_query(const cyc_batch* b, int32_t* kernel_cfg, int32_t* rounds, int32_t* graph);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,6 +34,62 @@ struct ContractArgs {
 
 enum { PREC_F32 = 0, PREC_BF16 = 1, PREC_F16 = 2 };
 
+// ---- batched (many stream states, one launch per kernel) ------------------
+// One contraction job: one chunk of one stream in one push (or the pending
+// partial chunk of one stream in a read).
+struct BJob {
+  VSrc v;              // the stream's virtual sample array for this call
+  int64_t v_off;       // virtual index of the chunk's first product
+  int64_t n_prod;      // products in the chunk (<= Kc)
+  int64_t abs_base;    // absolute sample index of the chunk's first product
+  const double* alpha_r;
+  const float2* H;
+  const float2* Lo;
+  float2* part;        // [2][T][A] chunk partial
+  double2* E;          // [A] chunk phase factor
+  int A;
+  int pad;
+};
+struct BItem {         // contraction work item
+  int job, tt, at, pad;
+};
+struct BAcc {          // S += sum of the stream's jobs [job0, job0 + njobs) in order
+  double2* S;
+  int64_t n2;          // 2*T*A
+  int job0, njobs, A, first;
+};
+struct BFin {          // read: out = (S + partial job * E) / n_used
+  const double2* S;
+  void* R;
+  void* Rc;
+  int64_t TA;
+  double nd;
+  int job;             // partial job or -1
+  int hasS, A, c128;
+};
+struct BCopy {         // dst[i] = v[shift + i], i < n
+  VSrc v;
+  int64_t shift, n;
+  float2* dst;
+};
+struct BTile {         // a block of 256 elements of descriptor `desc`
+  int desc, pad;
+  int64_t off;
+};
+// Counts live in device memory so one captured graph serves every call.
+struct BCounts {
+  int n_jobs, n_items, n_acc_tiles, n_copy_tiles, n_fin_tiles, counter, pad0, pad1;
+};
+struct BatchArgs {
+  const BJob* jobs;
+  const BItem* items;
+  const int* n_items;
+  int* counter;
+  int T, Kc;
+};
+
+typedef hipError_t (*BatchLaunch)(const BatchArgs&, int grid, hipStream_t);
+
 struct KernelCfg {
   int prec;      // PREC_*
   int split;     // modulated operand split into hi + lo
@@ -43,9 +99,19 @@ struct KernelCfg {
   int nthreads;  // workgroup size
   hipError_t (*launch)(const ContractArgs&, int grid, hipStream_t);
   const char* name;
+  // persistent batched form (nullptr if none) and its resident grid size
+  BatchLaunch blaunch;
+  int (*bgrid)();
 };
 
 const KernelCfg* kernel_cfgs(int* n);
+
+hipError_t launch_batch_small(const BJob* jobs, const BCounts* cnt, const BAcc* acc,
+                              const BTile* acc_tiles, const BCopy* copies,
+                              const BTile* copy_tiles, int* counter, int stage,
+                              hipStream_t st);
+hipError_t launch_batch_finalize(const BJob* jobs, const BFin* fin, const BTile* tiles,
+                                 const BCounts* cnt, hipStream_t st);
 
 hipError_t launch_tables(const double* alpha_r, int A, int ks, int nsteps, float2* Lo,
                          float2* H, hipStream_t st);

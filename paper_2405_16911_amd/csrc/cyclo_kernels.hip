@@ -207,8 +207,8 @@ struct Tile {
   TileId id;
   int tau0, alpha0, ns, nsteps;
   int64_t cbase, yend;
-  __device__ __forceinline__ Tile(const ContractArgs& a, int tw, int aw, int ks) {
-    id = tile_of(a);
+  __device__ __forceinline__ Tile(const ContractArgs& a, TileId tid_, int tw, int aw, int ks) {
+    id = tid_;
     tau0 = id.tt * tw;
     alpha0 = id.at * aw;
     cbase = a.v_off + (int64_t)id.chunk * a.Kc;
@@ -226,7 +226,7 @@ struct Tile {
 // Hankel value for row (t, cr) and component c: component (cr ^ c) of
 // x[s0+l+t], negated for cr = 0, c = 1.
 template <int TW, int AW, int WAVES_M, int WAVES_N, int KS>
-__global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_f32(ContractArgs a) {
+__device__ __forceinline__ void contract_f32_tile(const ContractArgs& a, TileId tid_in) {
   constexpr int NT = 64 * WAVES_M * WAVES_N;
   constexpr int MR = 2 * TW, NC = 2 * AW;
   constexpr int WM = MR / (32 * WAVES_M), WN = NC / (32 * WAVES_N);
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_f32(Contra
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
   const int h = lane >> 5, l32 = lane & 31;
-  const Tile tl(a, TW, AW, KS);
+  const Tile tl(a, tid_in, TW, AW, KS);
   const int ns = tl.ns;
 
   const int ga = tid % AW, gj = (tid / AW) * G;
@@ -344,7 +344,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_f32(Contra
 // eight 16-byte blocks that eight lanes write while staging, fall on disjoint
 // banks.
 template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS, int SCHED>
-__global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_16(ContractArgs a) {
+__device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId tid_in) {
   using O = Op<PREC>;
   constexpr int NT = 64 * WAVES_M * WAVES_N;
   constexpr int MR = 2 * TW, NC = 2 * AW;
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_16(Contrac
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
   const int h = lane >> 5, l32 = lane & 31;
-  const Tile tl(a, TW, AW, KS);
+  const Tile tl(a, tid_in, TW, AW, KS);
   const int ns = tl.ns;
 
   const int ga = tid % AW, gj = (tid / AW) * G;
@@ -502,6 +502,79 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_16(Contrac
   store_tiles<WM, WN, AW>(a, tl.id, tl.tau0, tl.alpha0, wm, wn, lane, acc);
 }
 
+// ----------------------------------------------------------------------------- kernels
+//
+// One workgroup per (chunk, lag tile, alpha tile) of one stream state, and a
+// persistent form for a batch of states: a fixed grid whose workgroups take
+// work items (job, lag tile, alpha tile) from an atomic counter until the
+// list is exhausted.  Every workgroup reaches the exit test each round, so the
+// grid drains whatever the number of items.
+template <int TW, int AW, int WAVES_M, int WAVES_N, int KS>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_f32(ContractArgs a) {
+  contract_f32_tile<TW, AW, WAVES_M, WAVES_N, KS>(a, tile_of(a));
+}
+
+template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS, int SCHED>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_16(ContractArgs a) {
+  contract_16_tile<PREC, SPLIT, TW, AW, WAVES_M, WAVES_N, KS, SCHED>(a, tile_of(a));
+}
+
+// Takes the next work item; all threads of the workgroup see the same value.
+__device__ __forceinline__ int next_item(int* counter) {
+  __shared__ int item;
+  __syncthreads();  // every thread has read the previous item
+  if (threadIdx.x == 0) item = atomicAdd(counter, 1);
+  __syncthreads();
+  return item;
+}
+
+__device__ __forceinline__ ContractArgs job_args(const BatchArgs& b, const BJob& j) {
+  ContractArgs a;
+  a.v = j.v;
+  a.v_off = j.v_off;
+  a.n_prod = j.n_prod;
+  a.T = b.T;
+  a.A = j.A;
+  a.Kc = b.Kc;
+  a.n_tt = 1;
+  a.n_at = 1;
+  a.n_chunks = 1;
+  a.H = j.H;
+  a.Lo = j.Lo;
+  a.part = j.part;
+  return a;
+}
+
+template <int TW, int AW, int WAVES_M, int WAVES_N, int KS>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_f32_batch(BatchArgs b) {
+  for (;;) {
+    const int it = next_item(b.counter);
+    if (it >= *b.n_items) break;
+    const BItem bi = b.items[it];
+    const BJob j = b.jobs[bi.job];
+    TileId id;
+    id.chunk = 0;
+    id.tt = bi.tt;
+    id.at = bi.at;
+    contract_f32_tile<TW, AW, WAVES_M, WAVES_N, KS>(job_args(b, j), id);
+  }
+}
+
+template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS, int SCHED>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_16_batch(BatchArgs b) {
+  for (;;) {
+    const int it = next_item(b.counter);
+    if (it >= *b.n_items) break;
+    const BItem bi = b.items[it];
+    const BJob j = b.jobs[bi.job];
+    TileId id;
+    id.chunk = 0;
+    id.tt = bi.tt;
+    id.at = bi.at;
+    contract_16_tile<PREC, SPLIT, TW, AW, WAVES_M, WAVES_N, KS, SCHED>(job_args(b, j), id);
+  }
+}
+
 // ----------------------------------------------------------------------------- register-B contraction
 //
 // BF16/FP16 variant for large lag tiles.  One wave per workgroup owns every
@@ -513,6 +586,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_16(Contrac
 // Accumulators: RB x 2NA blocks (Y blocks first, then Yc blocks).
 template <int PREC, int SPLIT, int RB, int NA, int KS>
 __global__ __launch_bounds__(64, 1) void contract_rg(ContractArgs a) {
+  const TileId tid_in = tile_of(a);
   using O = Op<PREC>;
   constexpr int NT = 64;
   constexpr int TW = 16 * RB, AW = 32 * NA;
@@ -533,7 +607,7 @@ __global__ __launch_bounds__(64, 1) void contract_rg(ContractArgs a) {
 
   const int tid = threadIdx.x, lane = tid;
   const int h = lane >> 5, l32 = lane & 31;
-  const Tile tl(a, TW, AW, KS);
+  const Tile tl(a, tid_in, TW, AW, KS);
   const int ns = tl.ns;
 
   // lane's cycle frequencies and the chunk-relative twiddles of the samples it
@@ -738,12 +812,46 @@ hipError_t launch_16(const ContractArgs& a, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int TW, int AW, int WAVES_M, int WAVES_N, int KS>
+hipError_t launch_f32_batch(const BatchArgs& b, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((contract_f32_batch<TW, AW, WAVES_M, WAVES_N, KS>), dim3(grid),
+                     dim3(64 * WAVES_M * WAVES_N), 0, st, b);
+  return hipGetLastError();
+}
+template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS, int SCHED>
+hipError_t launch_16_batch(const BatchArgs& b, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((contract_16_batch<PREC, SPLIT, TW, AW, WAVES_M, WAVES_N, KS, SCHED>),
+                     dim3(grid), dim3(64 * WAVES_M * WAVES_N), 0, st, b);
+  return hipGetLastError();
+}
+template <typename K>
+int resident_grid(K kernel, int threads) {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess)
+    return 0;
+  return ncu * (per > 0 ? per : 1);
+}
+template <int TW, int AW, int WAVES_M, int WAVES_N, int KS>
+int grid_f32_batch() {
+  return resident_grid(contract_f32_batch<TW, AW, WAVES_M, WAVES_N, KS>, 64 * WAVES_M * WAVES_N);
+}
+template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS, int SCHED>
+int grid_16_batch() {
+  return resident_grid(contract_16_batch<PREC, SPLIT, TW, AW, WAVES_M, WAVES_N, KS, SCHED>,
+                       64 * WAVES_M * WAVES_N);
+}
+
 #define CFG_F32(TW, AW, WMW, WNW, KS)                                                       \
   {PREC_F32, 0, TW, AW, KS, 64 * WMW * WNW, &launch_f32<TW, AW, WMW, WNW, KS>,              \
-   "f32_t" #TW "_a" #AW "_w" #WMW "x" #WNW "_k" #KS}
+   "f32_t" #TW "_a" #AW "_w" #WMW "x" #WNW "_k" #KS,                                        \
+   &launch_f32_batch<TW, AW, WMW, WNW, KS>, &grid_f32_batch<TW, AW, WMW, WNW, KS>}
 #define CFG_16(P, PN, SP, TW, AW, WMW, WNW, KS, SC)                                         \
   {P, SP, TW, AW, KS, 64 * WMW * WNW, &launch_16<P, SP, TW, AW, WMW, WNW, KS, SC>,          \
-   PN "_s" #SP "_t" #TW "_a" #AW "_w" #WMW "x" #WNW "_k" #KS "_i" #SC}
+   PN "_s" #SP "_t" #TW "_a" #AW "_w" #WMW "x" #WNW "_k" #KS "_i" #SC,                      \
+   &launch_16_batch<P, SP, TW, AW, WMW, WNW, KS, SC>,                                       \
+   &grid_16_batch<P, SP, TW, AW, WMW, WNW, KS, SC>}
 #define CFG_16_ALL(TW, AW, WMW, WNW, KS, SC)                \
   CFG_16(PREC_BF16, "bf16", 0, TW, AW, WMW, WNW, KS, SC),   \
   CFG_16(PREC_BF16, "bf16", 1, TW, AW, WMW, WNW, KS, SC),   \
@@ -752,7 +860,7 @@ hipError_t launch_16(const ContractArgs& a, int grid, hipStream_t st) {
 
 #define CFG_RG(P, PN, SP, RB, NA, KS)                                                      \
   {P, SP, 16 * RB, 32 * NA, KS, 64, &launch_rg<P, SP, RB, NA, KS>,                           \
-   PN "_s" #SP "_t" #RB "x16_a" #NA "x32_reg_k" #KS}
+   PN "_s" #SP "_t" #RB "x16_a" #NA "x32_reg_k" #KS, nullptr, nullptr}
 #define CFG_RG_ALL(RB, NA, KS)                  \
   CFG_RG(PREC_BF16, "bf16", 0, RB, NA, KS),     \
   CFG_RG(PREC_BF16, "bf16", 1, RB, NA, KS),     \
@@ -765,6 +873,7 @@ static const KernelCfg g_cfgs[] = {
     CFG_F32(64, 64, 2, 1, 16),
     CFG_F32(32, 64, 1, 2, 16),
     CFG_F32(64, 128, 2, 2, 16),
+    CFG_F32(64, 64, 2, 2, 16),
     CFG_16_ALL(128, 64, 4, 1, 32, 0),
     CFG_16_ALL(64, 64, 2, 1, 32, 0),
     CFG_16_ALL(32, 64, 1, 2, 32, 0),
@@ -773,6 +882,7 @@ static const KernelCfg g_cfgs[] = {
     CFG_16_ALL(128, 128, 4, 2, 32, 0),
     CFG_16_ALL(128, 128, 4, 2, 32, 1),
     CFG_16_ALL(128, 128, 2, 2, 32, 1),
+    CFG_16_ALL(64, 64, 2, 2, 32, 0),
     CFG_RG_ALL(8, 1, 32),
 };
 
@@ -886,6 +996,115 @@ hipError_t launch_pattern(float2* x, int64_t n, hipStream_t st) {
 __global__ void zero_kernel(uint32_t* p, int64_t nwords) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nwords) p[i] = 0u;
+}
+
+// ---- batched small kernels (grid-stride over device-resident descriptors) --
+
+__global__ void batch_reset_kernel(int* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+__global__ void batch_phase_kernel(const BJob* jobs, const BCounts* cnt) {
+  const int nj = cnt->n_jobs;
+  for (int j = blockIdx.x; j < nj; j += gridDim.x) {
+    const BJob jb = jobs[j];
+    for (int a = threadIdx.x; a < jb.A; a += blockDim.x) {
+      double s, c;
+      sincospi(2.0 * frac_prod(jb.alpha_r[a], jb.abs_base), &s, &c);
+      jb.E[a] = make_double2(c, -s);
+    }
+  }
+}
+
+__global__ void batch_accumulate_kernel(const BJob* jobs, const BAcc* acc, const BTile* tiles,
+                                        const BCounts* cnt) {
+  const int nt = cnt->n_acc_tiles;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    const BTile tl = tiles[t];
+    const BAcc d = acc[tl.desc];
+    const int64_t i = tl.off + threadIdx.x;
+    if (i >= d.n2) continue;
+    const int a = (int)(i % d.A);
+    double2 s = d.first ? make_double2(0.0, 0.0) : d.S[i];
+    for (int c = 0; c < d.njobs; ++c) {
+      const BJob& jb = jobs[d.job0 + c];
+      const float2 p = jb.part[i];
+      const double2 e = jb.E[a];
+      const double pr = p.x, pi = p.y;
+      s.x += pr * e.x - pi * e.y;
+      s.y += pr * e.y + pi * e.x;
+    }
+    d.S[i] = s;
+  }
+}
+
+__global__ void batch_copy_kernel(const BCopy* copies, const BTile* tiles, const BCounts* cnt) {
+  const int nt = cnt->n_copy_tiles;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    const BTile tl = tiles[t];
+    const BCopy d = copies[tl.desc];
+    const int64_t i = tl.off + threadIdx.x;
+    if (i < d.n) d.dst[i] = vload(d.v, d.shift + i);
+  }
+}
+
+__global__ void batch_finalize_kernel(const BJob* jobs, const BFin* fin, const BTile* tiles,
+                                      const BCounts* cnt) {
+  const int nt = cnt->n_fin_tiles;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    const BTile tl = tiles[t];
+    const BFin d = fin[tl.desc];
+    const int64_t i = tl.off + threadIdx.x;
+    if (i >= 2 * d.TA) continue;
+    const int table = i >= d.TA ? 1 : 0;
+    void* out = table ? d.Rc : d.R;
+    if (out == nullptr) continue;
+    const int64_t r = i - table * d.TA;
+    const int a = (int)(r % d.A);
+    double sr = 0.0, si = 0.0;
+    if (d.hasS) {
+      const double2 sv = d.S[i];
+      sr = sv.x;
+      si = sv.y;
+    }
+    if (d.job >= 0) {
+      const BJob& jb = jobs[d.job];
+      const float2 p = jb.part[i];
+      const double2 e = jb.E[a];
+      const double pr = p.x, pi = p.y;
+      sr += pr * e.x - pi * e.y;
+      si += pr * e.y + pi * e.x;
+    }
+    sr /= d.nd;
+    si /= d.nd;
+    if (d.c128)
+      reinterpret_cast<double2*>(out)[r] = make_double2(sr, si);
+    else
+      reinterpret_cast<float2*>(out)[r] = make_float2((float)sr, (float)si);
+  }
+}
+
+// stage 0: counter reset + phases (before the contraction);
+// stage 1: accumulation + pending-sample copies (after it).
+hipError_t launch_batch_small(const BJob* jobs, const BCounts* cnt, const BAcc* acc,
+                              const BTile* acc_tiles, const BCopy* copies,
+                              const BTile* copy_tiles, int* counter, int stage,
+                              hipStream_t st) {
+  if (stage == 0) {
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, st, counter);
+    hipLaunchKernelGGL(batch_phase_kernel, dim3(1024), dim3(256), 0, st, jobs, cnt);
+  } else {
+    hipLaunchKernelGGL(batch_accumulate_kernel, dim3(4096), dim3(256), 0, st, jobs, acc, acc_tiles,
+                       cnt);
+    hipLaunchKernelGGL(batch_copy_kernel, dim3(1024), dim3(256), 0, st, copies, copy_tiles, cnt);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(const BJob* jobs, const BFin* fin, const BTile* tiles,
+                                 const BCounts* cnt, hipStream_t st) {
+  hipLaunchKernelGGL(batch_finalize_kernel, dim3(4096), dim3(256), 0, st, jobs, fin, tiles, cnt);
+  return hipGetLastError();
 }
 
 static inline int nblocks(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }

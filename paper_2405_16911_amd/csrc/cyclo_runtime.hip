@@ -145,10 +145,20 @@ int pick_cfg(int prec, int split, int T, int A) {
     }
   }
   const int want_tw = T > 64 ? 128 : (T > 32 ? 64 : 32);
-  for (int i = 0; i < n; ++i)
-    if (c[i].prec == prec && c[i].split == split && c[i].tw == want_tw && c[i].aw == 64) return i;
-  return -1;
+  int best = -1;
+  for (int i = 0; i < n; ++i) {
+    if (c[i].prec != prec || c[i].split != split || c[i].tw != want_tw || c[i].aw != 64) continue;
+    if (best < 0 || (c[best].nthreads != 256 && c[i].nthreads == 256)) best = i;
+  }
+  return best;
 }
+
+}  // namespace
+
+// Shared with the batch runtime.
+int cyc_pick_cfg(int prec, int split, int T, int A) { return pick_cfg(prec, split, T, A); }
+
+namespace {
 
 void free_state(cyc_state* s) {
   if (!s) return;

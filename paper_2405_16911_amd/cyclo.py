@@ -49,6 +49,18 @@ SIGNATURES = {
     "cyc_autotune": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                                     ctypes.c_void_p]),
+    "cyc_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                        ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p]),
+    "cyc_batch_push": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+    "cyc_batch_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.c_void_p]),
+    "cyc_batch_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "cyc_batch_destroy": (None, [ctypes.c_void_p]),
+    "cyc_batch_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "cyc_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "cyc_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
@@ -223,6 +235,103 @@ class CyclicStream:
         if self._s is not None:
             cyc_destroy(self._s)
             self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------- batches
+
+def cyc_batch_create(alpha_lists, n_lag: int, flags: int = 0, stream=None) -> ctypes.c_void_p:
+    lists = [np.asarray(a, dtype=np.float64).reshape(-1) for a in alpha_lists]
+    offs = np.zeros(len(lists) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([a.size for a in lists])
+    flat = np.ascontiguousarray(np.concatenate(lists)) if lists else np.zeros(0)
+    out = ctypes.c_void_p()
+    code = lib().cyc_batch_create(ctypes.byref(out), len(lists),
+                                  offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  int(n_lag), int(flags), _stream_handle(stream))
+    _check(code, "cyc_batch_create")
+    return out
+
+
+def _ptr_array(tensors):
+    arr = (ctypes.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = t.data_ptr() if (t is not None and t.numel() > 0) else None
+    return arr
+
+
+def cyc_batch_push(batch, xs, stream=None):
+    """xs: one 1-D contiguous complex64 CUDA tensor (or None) per stream."""
+    import torch
+    for x in xs:
+        if x is not None and (x.dtype != torch.complex64 or not x.is_cuda or not x.is_contiguous()
+                              or x.dim() != 1):
+            raise ValueError("each x must be a contiguous 1-D complex64 CUDA tensor")
+    ns = (ctypes.c_int64 * len(xs))(*[0 if x is None else int(x.numel()) for x in xs])
+    _check(lib().cyc_batch_push(batch, _ptr_array(xs), ns, _stream_handle(stream)), "cyc_batch_push")
+
+
+def cyc_batch_read(batch, Rs=None, Rcs=None, n_streams=None, stream=None):
+    n = n_streams if n_streams is not None else len(Rs if Rs is not None else Rcs)
+    nu = (ctypes.c_int64 * n)()
+    pr = _ptr_array(Rs) if Rs is not None else None
+    prc = _ptr_array(Rcs) if Rcs is not None else None
+    _check(lib().cyc_batch_read(batch, pr, prc, nu, _stream_handle(stream)), "cyc_batch_read")
+    return [int(v) for v in nu]
+
+
+def cyc_batch_reset(batch):
+    _check(lib().cyc_batch_reset(batch), "cyc_batch_reset")
+
+
+def cyc_batch_destroy(batch):
+    lib().cyc_batch_destroy(batch)
+
+
+def cyc_batch_query(batch) -> dict:
+    cfg, rounds, graph = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().cyc_batch_query(batch, ctypes.byref(cfg), ctypes.byref(rounds), ctypes.byref(graph)),
+           "cyc_batch_query")
+    return dict(kernel_cfg=cfg.value, rounds=rounds.value, graph=bool(graph.value))
+
+
+class CyclicBatch:
+    """Many stream states with a common lag count, advanced together."""
+
+    def __init__(self, alpha_lists, n_lag: int, flags: int = 0, stream=None):
+        self.alphas = [np.asarray(a, dtype=np.float64).reshape(-1) for a in alpha_lists]
+        self.T = int(n_lag)
+        self.flags = int(flags)
+        self._b = cyc_batch_create(self.alphas, self.T, self.flags, stream)
+
+    def push(self, xs, stream=None):
+        cyc_batch_push(self._b, xs, stream)
+
+    def read(self, stream=None):
+        """Returns ([R_s], [Rc_s], [n_used_s]) as new [T, A_s] tensors on the GPU."""
+        import torch
+        dt = torch.complex128 if self.flags & CYC_OUT_C128 else torch.complex64
+        Rs = [torch.empty((self.T, a.size), dtype=dt, device="cuda") for a in self.alphas]
+        Rcs = [torch.empty_like(r) for r in Rs]
+        nu = cyc_batch_read(self._b, Rs, Rcs, stream=stream)
+        return Rs, Rcs, nu
+
+    def reset(self):
+        cyc_batch_reset(self._b)
+
+    def query(self) -> dict:
+        return cyc_batch_query(self._b)
+
+    def close(self):
+        if self._b is not None:
+            cyc_batch_destroy(self._b)
+            self._b = None
 
     def __del__(self):
         try:

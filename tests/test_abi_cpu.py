@@ -91,3 +91,23 @@ def test_kernel_configurations_enumerate(L):
     assert L.cyc_kernel_cfg_info(-1, None, None, None, None, None) == cyclo.CYC_EINVAL
     assert L.cyc_set_kernel_cfg(None, 0) == cyclo.CYC_EINVAL
     assert L.cyc_autotune(0, 4, 0, None, None, None) == cyclo.CYC_EINVAL
+
+
+def test_batch_invalid_arguments(L):
+    out = ctypes.c_void_p()
+    a = (ctypes.c_double * 3)(0.0, 0.1, 0.2)
+    offs = (ctypes.c_int64 * 3)(0, 2, 3)
+    bad_offs = (ctypes.c_int64 * 3)(0, 0, 3)
+    assert L.cyc_batch_create(None, 2, offs, a, 4, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_batch_create(ctypes.byref(out), 0, offs, a, 4, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_batch_create(ctypes.byref(out), 2, bad_offs, a, 4, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_batch_create(ctypes.byref(out), 2, offs, a, 0, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_batch_create(ctypes.byref(out), 2, offs, a, 4, cyclo.CYC_TW_SPLIT, None) == cyclo.CYC_EUNSUPPORTED
+    nan = (ctypes.c_double * 3)(0.0, float("nan"), 0.2)
+    assert L.cyc_batch_create(ctypes.byref(out), 2, offs, nan, 4, 0, None) == cyclo.CYC_EINVAL
+    assert out.value is None
+    assert L.cyc_batch_push(None, None, None, None) == cyclo.CYC_EINVAL
+    assert L.cyc_batch_read(None, None, None, None, None) == cyclo.CYC_EINVAL
+    assert L.cyc_batch_reset(None) == cyclo.CYC_EINVAL
+    assert L.cyc_batch_query(None, None, None, None) == cyclo.CYC_EINVAL
+    L.cyc_batch_destroy(None)
