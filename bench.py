@@ -108,6 +108,80 @@ def cpu_baseline(wl, n_samples: int):
                        f"host {platform.processor() or platform.machine()}")
 
 
+def batch_workload(n_streams: int = 512, seed: int = 4, T: int = 64):
+    """Mixed-modulation batch: uneven lengths (log-uniform 2^12..2^20) and alpha sets."""
+    from paper_2405_16911_amd import siggen
+    xs, alists, metas = [], [], []
+    for s in range(n_streams):
+        x, m = siggen.mixed_stream(seed, s)
+        xs.append(x)
+        alists.append(siggen.uniform_grid(m["n_alpha"], -0.5))
+        metas.append(m)
+    return dict(xs=xs, alists=alists, T=T, metas=metas,
+                desc=f"mixed_{n_streams}streams_T{T}_L2^12-2^20_A64-2048")
+
+
+def run_batch(bw, prec: str, steps: int, warmup: int, compare_single: bool = False):
+    """One step = reset, one batched push of every stream's record, batched read."""
+    import torch
+    from paper_2405_16911_amd import cyclo
+    flags = PREC_FLAGS[prec]
+    T = bw["T"]
+    dev = [torch.from_numpy(x).to("cuda") for x in bw["xs"]]
+    b = cyclo.CyclicBatch(bw["alists"], T, flags)
+    Rs = [torch.empty((T, a.size), dtype=torch.complex64, device="cuda") for a in bw["alists"]]
+    Rcs = [torch.empty_like(r) for r in Rs]
+
+    def step():
+        b.reset()
+        b.push(dev)
+        return cyclo.cyc_batch_read(b._b, Rs, Rcs)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        nu = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    q = b.query()
+    b.close()
+    work = float(sum(a.size * T * n for a, n in zip(bw["alists"], nu)))
+    out = dict(dtype=prec, value=work / dt, ms_per_step=1e3 * dt, work=work,
+               kernel_cfg=cyclo.cyc_kernel_cfg_info(q["kernel_cfg"])["name"],
+               rounds_per_push=q["rounds"], graph=q["graph"],
+               mfma_frac_whole_path=FLOPS_PER_TRIPLE * work / dt / 1e12 / PEAK_TFLOPS[prec])
+    if compare_single:
+        # the same work as one single-state push per stream, back to back
+        old = os.environ.get("CYC_WORKSPACE_MB")
+        os.environ["CYC_WORKSPACE_MB"] = "8"  # 512 states: keep each workspace small
+        try:
+            states = [cyclo.CyclicStream(a, T, flags) for a in bw["alists"]]
+        finally:
+            if old is None:
+                os.environ.pop("CYC_WORKSPACE_MB", None)
+            else:
+                os.environ["CYC_WORKSPACE_MB"] = old
+        for _ in range(max(1, warmup)):
+            for st, d in zip(states, dev):
+                st.reset()
+                st.push(d)
+                cyclo.cyc_read(st._s, None, None)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for st, d, R, Rc in zip(states, dev, Rs, Rcs):
+                st.reset()
+                st.push(d)
+                cyclo.cyc_read(st._s, R, Rc)
+        torch.cuda.synchronize()
+        out["single_state_loop_ms_per_step"] = 1e3 * (time.perf_counter() - t0) / steps
+        for st in states:
+            st.close()
+    return out
+
+
 def copy_calibration(nbytes: int = 256 << 20, reps: int = 5):
     """A plain copy kernel of known size: reads and writes nbytes per launch."""
     import torch
@@ -132,6 +206,9 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=1 << 21)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--forms", default="batch",
+                    help="extra forms measured after the main workload: 'batch' or ''")
+    ap.add_argument("--batch-streams", type=int, default=512)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain elementwise copy of 256 MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -182,6 +259,16 @@ def main():
                      / max(1, prof["launches"])},
         "variants": variants,
     }
+    forms = {}
+    if "batch" in args.forms.split(","):
+        bw = batch_workload(args.batch_streams)
+        forms["batch"] = dict(workload=bw["desc"], n_streams=len(bw["xs"]),
+                              n_samples=int(sum(x.size for x in bw["xs"])),
+                              runs=[run_batch(bw, "bf16", 3, 1, compare_single=True),
+                                    run_batch(bw, "f32", 2, 1)])
+        del bw
+    if forms:
+        out["forms"] = forms
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_samples)
     print(json.dumps(out), flush=True)

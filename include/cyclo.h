@@ -153,9 +153,10 @@ int cyc_kernel_cfg_info(int32_t idx, uint32_t* flags, int32_t* lag_tile, int32_t
 int cyc_set_kernel_cfg(cyc_state* s, int32_t idx);
 
 /*
- * Autotuner.  Times every configuration that implements `flags` on one push of
- * synthetic samples into a state of n_alpha cycle frequencies and n_lag lags
- * (HIP events on `stream`), and records the fastest in the tuning cache under
+ * Autotuner.  Times every configuration that implements `flags` on pushes of
+ * synthetic samples (16 chunks each) into a state of n_alpha cycle
+ * frequencies and n_lag lags (HIP events on `stream`, median of 7 pushes after
+ * a warm-up), and records the fastest in the tuning cache under
  * (device architecture, precision, split, n_lag, ceil(log2 n_alpha)).
  * cyc_create consults the cache.  If the environment variable CYC_TUNE_CACHE
  * names a file, the cache is loaded from it on first use and every new entry
@@ -192,8 +193,10 @@ int cyc_autotune(int32_t n_alpha, int32_t n_lag, uint32_t flags, int32_t* best_c
  *               (either array, or any entry, may be NULL to skip).
  *   n_used    : host array of n_streams (may be NULL).
  * Errors: as the single-stream calls.  The batch allocates its descriptor
- * tables and workspace at creation (CYC_WORKSPACE_MB bounds the partial-sum
- * workspace; larger pushes are processed in several rounds).
+ * tables and workspace at creation (CYC_WORKSPACE_MB, default 1024, bounds the
+ * partial-sum workspace; larger pushes are processed in several rounds).  The
+ * chunk length (CYC_CHUNK) defaults to 4096 products for FP32 operands and
+ * 16384 for BF16/FP16.
  */
 typedef struct cyc_batch cyc_batch;
 int cyc_batch_create(cyc_batch** out, int32_t n_streams, const int64_t* alpha_offsets,

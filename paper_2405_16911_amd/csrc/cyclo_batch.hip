@@ -318,7 +318,10 @@ int cyc_batch_create(cyc_batch** out, int32_t n_streams, const int64_t* alpha_of
   }
   const KernelCfg& cfg = cfgs[b->cfg];
   b->KS = cfg.ks;
-  int64_t kc = env_i64b("CYC_CHUNK", 4096);
+  // Batches have parallelism across streams, so 16-bit operands use longer
+  // chunks (fewer partial sums to write and fold); FP32 keeps 4096 products
+  // per FP32-accumulated chunk for its accuracy budget.
+  int64_t kc = env_i64b("CYC_CHUNK", prec == PREC_F32 ? 4096 : 16384);
   kc = std::max<int64_t>(cfg.ks, std::min<int64_t>(kc, 1 << 20));
   kc = (kc / cfg.ks) * cfg.ks;
   b->Kc = (int)kc;
@@ -335,7 +338,7 @@ int cyc_batch_create(cyc_batch** out, int32_t n_streams, const int64_t* alpha_of
   }
   b->ATMAX = (int)at;
   b->CTMAX = (int)ct;
-  const int64_t ws_bytes = env_i64b("CYC_WORKSPACE_MB", 256) << 20;
+  const int64_t ws_bytes = env_i64b("CYC_WORKSPACE_MB", 1024) << 20;
   b->part_cap = std::max<int64_t>(2 * (int64_t)b->T * amax, ws_bytes / 8);
   b->E_cap = std::max<int64_t>(amax, b->part_cap / (2 * (int64_t)b->T));
   b->JMAX = 32768;

@@ -486,8 +486,9 @@ int cyc_autotune(int32_t n_alpha, int32_t n_lag, uint32_t flags, int32_t* best_c
   double bms = 1e300;
   for (int i = 0; i < n && rc == CYC_OK; ++i) {
     if (c[i].prec != prec || c[i].split != split || cyc_set_kernel_cfg(s, i) != CYC_OK) continue;
-    double ms_min = 1e300;
-    for (int rep = 0; rep < 4 && rc == CYC_OK; ++rep) {
+    // median of 7 timed pushes after one warm-up push
+    std::vector<double> ts;
+    for (int rep = 0; rep < 8 && rc == CYC_OK; ++rep) {
       cyc_reset(s);
       float t = 0.f;
       if (hipEventRecord(e0, st) != hipSuccess || cyc_push(s, x, nsamp, stream) != CYC_OK ||
@@ -496,11 +497,15 @@ int cyc_autotune(int32_t n_alpha, int32_t n_lag, uint32_t flags, int32_t* best_c
         rc = CYC_EDEVICE;
         break;
       }
-      if (rep > 0) ms_min = std::min(ms_min, (double)t);
+      if (rep > 0) ts.push_back((double)t);
     }
-    if (rc == CYC_OK && ms_min < bms) {
-      bms = ms_min;
-      best = i;
+    if (rc == CYC_OK) {
+      std::sort(ts.begin(), ts.end());
+      const double med = ts[ts.size() / 2];
+      if (med < bms) {
+        bms = med;
+        best = i;
+      }
     }
   }
   if (e0) (void)hipEventDestroy(e0);
