@@ -1,0 +1,184 @@
+"""FP64 CPU oracle for the learned cycle-frequency proposal.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/cyclic.py``); shares no code with the
+HIP path.
+
+The paper's related-work discussion (Sec. 1) describes a two-stage estimator:
+a coarse stage locates cyclic features and a fine stage evaluates the
+estimator only near them; cycle-frequency estimation is named as future work
+(Sec. 6).  This module holds the plain definitions of every step of the
+learned form of that coarse stage:
+
+* features: Welch spectra (Hann window, non-overlapping segments, averaged
+  squared magnitude) of x, x^2 and |x|^2, shifted to [-1/2, 1/2), log, then
+  standardised per channel;
+* the network: circular 1-D convolutions with ReLU, then a dense layer over
+  the flattened channels x positions and a sigmoid per coarse bin;
+* binary cross-entropy loss (mean over windows and bins), its gradients by
+  the chain rule, and one AdamW step;
+* labels: coarse bins holding a peak of the full-grid tables;
+* selection: top-k coarse bins, each widened by +-w bins circularly, the
+  coarse bin of alpha = 0 always included, and the confidence rule.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# ----------------------------------------------------------------------------- features
+
+
+def hann(n: int) -> np.ndarray:
+    """Periodic Hann window w[i] = 1/2 - 1/2 cos(2 pi i / n)."""
+    return 0.5 - 0.5 * np.cos(2.0 * np.pi * np.arange(n) / n)
+
+
+def welch_log_spectra(x, nseg: int = 64, nfft: int = 1024, eps: float = 1e-12) -> np.ndarray:
+    """(3, nfft) standardised log spectra of x, x^2, |x|^2 (bins f = -1/2 + m/nfft)."""
+    x = np.asarray(x).astype(np.complex128).reshape(-1)[: nseg * nfft]
+    w = hann(nfft)
+    out = np.empty((3, nfft))
+    for c, v in enumerate((x, x * x, (np.abs(x) ** 2).astype(np.complex128))):
+        segs = v.reshape(nseg, nfft) * w[None, :]
+        P = np.mean(np.abs(np.fft.fft(segs, axis=1)) ** 2, axis=0)
+        L = np.log(np.fft.fftshift(P) + eps)
+        out[c] = (L - L.mean()) / (L.std() + 1e-12)
+    return out
+
+
+# ----------------------------------------------------------------------------- network
+
+
+def init_params(rng, C_in=3, C=64, K=7, L=1024, n_out=1024, n_conv=4):
+    """He-style initial weights (FP64)."""
+    p = {}
+    cin = C_in
+    for i in range(n_conv):
+        p[f"W{i}"] = rng.standard_normal((C, cin, K)) * np.sqrt(2.0 / (cin * K))
+        p[f"b{i}"] = np.zeros(C)
+        cin = C
+    p["Wh"] = rng.standard_normal((n_out, C * L)) * np.sqrt(1.0 / (C * L))
+    p["bh"] = np.zeros(n_out)
+    return p
+
+
+def conv_circ(x, W, b):
+    """y[n, o, t] = b[o] + sum_{i,k} W[o, i, k] x[n, i, (t + k - K//2) mod L]."""
+    K = W.shape[2]
+    L = x.shape[2]
+    y = np.broadcast_to(b[None, :, None], (x.shape[0], W.shape[0], L)).copy()
+    for k in range(K):
+        xs = np.roll(x, -(k - K // 2), axis=2)   # xs[..., t] = x[..., t + k - K//2]
+        y += np.einsum("oi,nit->not", W[:, :, k], xs)
+    return y
+
+
+def conv_circ_backward(x, W, dy):
+    """Gradients of conv_circ w.r.t. x, W and b for upstream gradient dy."""
+    K = W.shape[2]
+    dW = np.empty_like(W)
+    dx = np.zeros_like(x)
+    for k in range(K):
+        xs = np.roll(x, -(k - K // 2), axis=2)
+        dW[:, :, k] = np.einsum("not,nit->oi", dy, xs)
+        # y[t] gets x[t + s], s = k - K//2, so x[u] feeds y[u - s]
+        dx += np.roll(np.einsum("oi,not->nit", W[:, :, k], dy), (k - K // 2), axis=2)
+    db = dy.sum(axis=(0, 2))
+    return dx, dW, db
+
+
+def sigmoid(z):
+    return 1.0 / (1.0 + np.exp(-z))
+
+
+def forward(p, X, n_conv=4):
+    """Returns (logits z (N, n_out), cache)."""
+    acts = [X]
+    pre = []
+    a = X
+    for i in range(n_conv):
+        u = conv_circ(a, p[f"W{i}"], p[f"b{i}"])
+        pre.append(u)
+        a = np.maximum(u, 0.0)
+        acts.append(a)
+    h = a.reshape(a.shape[0], -1)           # h[n, c*L + t] = a[n, c, t]
+    z = h @ p["Wh"].T + p["bh"][None, :]
+    return z, dict(acts=acts, pre=pre, h=h)
+
+
+def bce_loss(z, y):
+    """Mean binary cross-entropy of sigmoid(z) against labels y, computed stably."""
+    return float(np.mean(np.maximum(z, 0) - z * y + np.log1p(np.exp(-np.abs(z)))))
+
+
+def backward(p, cache, z, y, n_conv=4):
+    """Gradients of bce_loss(forward(p, X)) with respect to every parameter."""
+    g = {}
+    dz = (sigmoid(z) - y) / z.size
+    g["Wh"] = dz.T @ cache["h"]
+    g["bh"] = dz.sum(axis=0)
+    dh = dz @ p["Wh"]
+    da = dh.reshape(cache["acts"][-1].shape)
+    for i in reversed(range(n_conv)):
+        du = da * (cache["pre"][i] > 0)
+        dx, g[f"W{i}"], g[f"b{i}"] = conv_circ_backward(cache["acts"][i], p[f"W{i}"], du)
+        da = dx
+    return g
+
+
+def adamw_step(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, wd=1e-2):
+    """One AdamW update (decoupled weight decay) in place; t is the 1-based step."""
+    for k in p:
+        m[k] = b1 * m[k] + (1 - b1) * g[k]
+        v[k] = b2 * v[k] + (1 - b2) * g[k] * g[k]
+        mh = m[k] / (1 - b1 ** t)
+        vh = v[k] / (1 - b2 ** t)
+        p[k] = p[k] - lr * (mh / (np.sqrt(vh) + eps) + wd * p[k])
+
+
+# ----------------------------------------------------------------------------- labels and selection
+
+
+def peak_cells(R, thresh: float = 7.0):
+    """|R[t, a]| / sigma_t > thresh with sigma_t = mean_a |R[t, a]| / sqrt(pi/2).
+
+    For noise-only cells |R| is Rayleigh distributed with mean sigma*sqrt(pi/2);
+    a few feature cells among many alphas move the mean very little.
+    """
+    m = np.abs(R)
+    sigma = np.mean(m, axis=1, keepdims=True) / np.sqrt(np.pi / 2.0)
+    return m > thresh * np.maximum(sigma, 1e-300)
+
+
+def coarse_labels(R, Rc, n_coarse: int, zero_bin: int, thresh: float = 7.0) -> np.ndarray:
+    """Coarse bin positive if any of its fine bins peaks at any lag in either table.
+
+    The coarse bin holding alpha = 0 is excluded for the non-conjugate table
+    (the power term is always there; that bin is always evaluated).
+    """
+    A = R.shape[1]
+    per = A // n_coarse
+    pk = peak_cells(R, thresh).any(axis=0).reshape(n_coarse, per).any(axis=1)
+    pkc = peak_cells(Rc, thresh).any(axis=0).reshape(n_coarse, per).any(axis=1)
+    pk[zero_bin] = False
+    return (pk | pkc).astype(np.float64)
+
+
+def select(prob, k: int = 16, width: int = 2, zero_bin: int | None = None):
+    """Top-k bins (ties -> lower index), each widened by +-width circularly, sorted.
+
+    Returns (selected bins, confidence = 1 - max probability outside the set).
+    """
+    prob = np.asarray(prob, dtype=np.float64)
+    n = prob.size
+    order = np.lexsort((np.arange(n), -prob))   # descending prob, then ascending index
+    sel = set()
+    for i in order[:k]:
+        for d in range(-width, width + 1):
+            sel.add(int((i + d) % n))
+    if zero_bin is not None:
+        sel.add(int(zero_bin))
+    sel = np.array(sorted(sel), dtype=np.int64)
+    mask = np.ones(n, bool)
+    mask[sel] = False
+    conf = 1.0 - (prob[mask].max() if mask.any() else 0.0)
+    return sel, conf

@@ -1,0 +1,100 @@
+"""Pins of the proposal oracle (no GPU): finite differences for every gradient,
+the convolution against a direct loop, AdamW against a hand-stepped scalar,
+spectra against a tone's known line, and selection corner cases."""
+import numpy as np
+import pytest
+
+from oracle import proposal as P
+
+
+def _tiny(seed=0, N=3, C_in=3, C=4, K=7, L=16, n_out=5, n_conv=2):
+    rng = np.random.default_rng(seed)
+    p = P.init_params(rng, C_in=C_in, C=C, K=K, L=L, n_out=n_out, n_conv=n_conv)
+    for k in p:
+        if k.startswith("b"):
+            p[k] = rng.standard_normal(p[k].shape) * 0.1
+    X = rng.standard_normal((N, C_in, L))
+    y = (rng.random((N, n_out)) < 0.3).astype(float)
+    return p, X, y
+
+
+def test_conv_against_direct_loop():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((2, 3, 9))
+    W = rng.standard_normal((4, 3, 5))
+    b = rng.standard_normal(4)
+    y = P.conv_circ(x, W, b)
+    for n in range(2):
+        for o in range(4):
+            for t in range(9):
+                ref = b[o] + sum(W[o, i, k] * x[n, i, (t + k - 2) % 9] for i in range(3) for k in range(5))
+                assert abs(y[n, o, t] - ref) < 1e-12
+
+
+def test_gradients_by_central_differences():
+    n_conv = 2
+    p, X, y = _tiny(n_conv=n_conv)
+    z, cache = P.forward(p, X, n_conv)
+    g = P.backward(p, cache, z, y, n_conv)
+    h = 1e-6
+    rng = np.random.default_rng(2)
+    for k in p:
+        flat = p[k].reshape(-1)
+        for idx in rng.choice(flat.size, size=min(6, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp = P.bce_loss(P.forward(p, X, n_conv)[0], y)
+            flat[idx] = old - h
+            lm = P.bce_loss(P.forward(p, X, n_conv)[0], y)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            an = g[k].reshape(-1)[idx]
+            assert abs(fd - an) <= 1e-6 * max(1e-4, abs(fd)) + 1e-9, (k, idx, fd, an)
+
+
+def test_adamw_first_steps_scalar():
+    p = {"w": np.array([0.5])}
+    g = {"w": np.array([0.2])}
+    m = {"w": np.zeros(1)}
+    v = {"w": np.zeros(1)}
+    P.adamw_step(p, g, m, v, 1, lr=0.1, wd=0.01)
+    # bias-corrected first step: m_hat = g, v_hat = g^2 -> step lr * (sign(g) + wd * w)
+    assert abs(p["w"][0] - (0.5 - 0.1 * (0.2 / (0.2 + 1e-8) + 0.01 * 0.5))) < 1e-12
+
+
+def test_spectra_of_a_tone():
+    f = 37 / 1024                       # on a bin
+    n = np.arange(64 * 1024)
+    x = np.exp(2j * np.pi * f * n)
+    S = P.welch_log_spectra(x)
+    assert np.argmax(S[0]) == 512 + 37       # x: line at f
+    assert np.argmax(S[1]) == 512 + 74       # x^2: line at 2f
+    assert np.argmax(S[2]) == 512            # |x|^2 = 1: line at 0
+    for c in range(3):
+        assert abs(S[c].mean()) < 1e-9 and abs(S[c].std() - 1) < 1e-6
+
+
+def test_selection_ties_wrap_and_zero_bin():
+    p = np.zeros(32)
+    p[[0, 5, 31]] = 0.9                       # tie: lower indices first
+    p[10] = 0.95
+    sel, conf = P.select(p, k=3, width=1, zero_bin=16)
+    assert list(sel) == [0, 1, 4, 5, 6, 9, 10, 11, 16, 31]   # 31 is 0's circular neighbour
+    assert conf == 1.0
+    sel1, conf1 = P.select(p, k=3, width=0, zero_bin=16)
+    assert list(sel1) == [0, 5, 10, 16]
+    assert abs(conf1 - (1 - 0.9)) < 1e-12     # bin 31 (0.9) was left out
+    sel2, conf2 = P.select(p, k=4, width=1)
+    assert 30 in sel2 and 31 in sel2 and conf2 == 1.0
+
+
+def test_labels_exclude_power_bin():
+    rng = np.random.default_rng(3)
+    A, n_coarse = 256, 16
+    R = (rng.standard_normal((4, A)) + 1j * rng.standard_normal((4, A))) * 0.01
+    Rc = R.copy() * 0.5
+    R[:, 128] = 5.0          # power term at alpha = 0 (coarse bin 8)
+    R[2, 40] = 1.0           # a feature in coarse bin 2
+    Rc[0, 250] = 1.0         # a conjugate feature in coarse bin 15
+    lab = P.coarse_labels(R, Rc, n_coarse, zero_bin=8)
+    assert list(np.nonzero(lab)[0]) == [2, 15]
