@@ -210,6 +210,63 @@ void cyc_batch_destroy(cyc_batch* b);
  * the last push replayed a captured graph (outputs may be NULL). */
 int cyc_batch_query(const cyc_batch* b, int32_t* kernel_cfg, int32_t* rounds, int32_t* graph);
 
+/*
+ * Learned cycle-frequency proposal (coarse stage of a coarse-to-fine
+ * estimator; the paper's related work in Sec. 1 describes the two-stage idea
+ * and Sec. 6 names cycle-frequency estimation as future work).
+ *
+ * Features: for each window of 65536 complex64 samples, Welch spectra
+ * (64 Hann-windowed segments of 1024, averaged |FFT|^2) of x, x^2 and |x|^2,
+ * shifted to frequencies -1/2 + m/1024, log, standardised per channel.
+ * Layout of a feature batch: float [3][n_windows][1024] (channel-major).
+ * Network: 4 circular conv1d layers (64 channels, kernel 7, ReLU), then a
+ * dense 65536 -> 1024 layer and a sigmoid: probability that coarse bin k
+ * (cycle frequencies [-1/2 + k/1024, -1/2 + (k+1)/1024)) holds a feature.
+ * Parameters: one FP32 vector of cyc_model_num_params() values, in the order
+ * W0[64][3][7], b0[64], W1[64][64][7], b1, W2, b2, W3, b3, Wh[1024][65536],
+ * bh[1024].  flags: CYC_OP_FP32 or CYC_OP_BF16 operands for every matrix
+ * product (FP32 accumulation, FP32 master weights and AdamW moments).
+ * max_batch bounds n_windows of every call (activations are allocated at
+ * creation).  All d_* pointers are device memory.  Errors: CYC_EINVAL,
+ * CYC_EUNSUPPORTED (other precisions), CYC_ENOMEM, CYC_EDEVICE.
+ */
+typedef struct cyc_model cyc_model;
+int64_t cyc_model_num_params(void);
+int cyc_model_create(cyc_model** out, int32_t max_batch, uint32_t flags, void* stream);
+void cyc_model_destroy(cyc_model* m);
+/* Copy FP32 parameters from / to host memory (set also clears the AdamW state). */
+int cyc_model_set_params(cyc_model* m, const float* host, void* stream);
+int cyc_model_get_params(cyc_model* m, float* host, void* stream);
+/* d_x: n_windows * 65536 complex64 samples -> d_feat [3][n_windows][1024]. */
+int cyc_model_spectra(cyc_model* m, const void* d_x, int32_t n_windows, float* d_feat, void* stream);
+/* d_prob: [n][1024] probabilities. */
+int cyc_model_forward(cyc_model* m, const float* d_feat, int32_t n, float* d_prob, void* stream);
+/* Gradients of the mean binary cross-entropy against d_labels [n][1024] (0/1)
+ * into d_grad (num_params floats, may be NULL); *loss (host, may be NULL). */
+int cyc_model_gradients(cyc_model* m, const float* d_feat, const float* d_labels, int32_t n,
+                        float* d_grad, double* loss, void* stream);
+/* One AdamW step (beta1 0.9, beta2 0.999, eps 1e-8, decoupled weight decay). */
+int cyc_model_train_step(cyc_model* m, const float* d_feat, const float* d_labels, int32_t n,
+                         float lr, float weight_decay, double* loss, void* stream);
+/*
+ * Selection: per window, the topk coarse bins of d_prob [n][1024] (ties ->
+ * lower index), each widened by +-width bins circularly, plus zero_bin (-1 for
+ * none) -> d_sel [n][1024] (1 = evaluate), and d_conf [n] = 1 - the largest
+ * probability outside the selection (fall back to the full grid below a
+ * threshold).
+ */
+int cyc_select(const float* d_prob, int32_t n, int32_t topk, int32_t width, int32_t zero_bin,
+               uint8_t* d_sel, float* d_conf, void* stream);
+/*
+ * Labels from full-grid tables: d_R, d_Rc complex64 [n_lag][n_alpha] of one
+ * window, n_alpha = n_coarse * (fine bins per coarse bin).  Coarse bin c is 1
+ * if some fine bin of it has |R| > thresh * sigma_t at some lag t in either
+ * table, sigma_t = mean over alpha of |R[t][.]| / sqrt(pi/2) (the Rayleigh
+ * scale of noise-only cells); the non-conjugate table is ignored in zero_bin.
+ */
+int cyc_peak_labels(const void* d_R, const void* d_Rc, int32_t n_lag, int32_t n_alpha,
+                    int32_t n_coarse, int32_t zero_bin, float thresh, float* d_labels, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -61,6 +61,26 @@ SIGNATURES = {
     "cyc_batch_destroy": (None, [ctypes.c_void_p]),
     "cyc_batch_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "cyc_model_num_params": (ctypes.c_int64, []),
+    "cyc_model_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_uint32,
+                                        ctypes.c_void_p]),
+    "cyc_model_destroy": (None, [ctypes.c_void_p]),
+    "cyc_model_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cyc_model_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cyc_model_spectra": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
+    "cyc_model_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
+    "cyc_model_gradients": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                           ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "cyc_model_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_float, ctypes.c_float, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.c_void_p]),
+    "cyc_select": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cyc_peak_labels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
     "cyc_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "cyc_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
@@ -338,3 +358,105 @@ class CyclicBatch:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------------------- learned proposal
+
+WINDOW = 65536
+N_COARSE = 1024
+FEAT_LEN = 1024
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class ProposalModel:
+    """The proposal network (features, forward, gradients, AdamW) on the GPU."""
+
+    def __init__(self, max_batch: int, flags: int = CYC_OP_BF16, stream=None):
+        self.max_batch = int(max_batch)
+        self.flags = int(flags)
+        out = ctypes.c_void_p()
+        _check(lib().cyc_model_create(ctypes.byref(out), self.max_batch, self.flags, _stream_handle(stream)),
+               "cyc_model_create")
+        self._m = out
+
+    @staticmethod
+    def num_params() -> int:
+        return int(lib().cyc_model_num_params())
+
+    def set_params(self, flat: np.ndarray, stream=None):
+        a = np.ascontiguousarray(np.asarray(flat, dtype=np.float32).reshape(-1))
+        if a.size != self.num_params():
+            raise ValueError("wrong parameter count")
+        _check(lib().cyc_model_set_params(self._m, a.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream)),
+               "cyc_model_set_params")
+
+    def get_params(self, stream=None) -> np.ndarray:
+        a = np.empty(self.num_params(), dtype=np.float32)
+        _check(lib().cyc_model_get_params(self._m, a.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream)),
+               "cyc_model_get_params")
+        return a
+
+    def spectra(self, x, stream=None):
+        """x: complex64 CUDA tensor of n*65536 samples -> float tensor [3, n, 1024]."""
+        import torch
+        n = x.numel() // WINDOW
+        feat = torch.empty((3, n, FEAT_LEN), dtype=torch.float32, device=x.device)
+        _check(lib().cyc_model_spectra(self._m, _p(x), n, _p(feat), _stream_handle(stream)), "cyc_model_spectra")
+        return feat
+
+    def forward(self, feat, stream=None):
+        import torch
+        n = feat.shape[1]
+        prob = torch.empty((n, N_COARSE), dtype=torch.float32, device=feat.device)
+        _check(lib().cyc_model_forward(self._m, _p(feat), n, _p(prob), _stream_handle(stream)), "cyc_model_forward")
+        return prob
+
+    def gradients(self, feat, labels, stream=None):
+        import torch
+        g = torch.empty(self.num_params(), dtype=torch.float32, device=feat.device)
+        loss = ctypes.c_double()
+        _check(lib().cyc_model_gradients(self._m, _p(feat), _p(labels), feat.shape[1], _p(g), ctypes.byref(loss),
+                                         _stream_handle(stream)), "cyc_model_gradients")
+        return g, loss.value
+
+    def train_step(self, feat, labels, lr: float, weight_decay: float, stream=None) -> float:
+        loss = ctypes.c_double()
+        _check(lib().cyc_model_train_step(self._m, _p(feat), _p(labels), feat.shape[1], float(lr),
+                                          float(weight_decay), ctypes.byref(loss), _stream_handle(stream)),
+               "cyc_model_train_step")
+        return loss.value
+
+    def close(self):
+        if self._m is not None:
+            lib().cyc_model_destroy(self._m)
+            self._m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cyc_select(prob, topk: int = 16, width: int = 2, zero_bin: int = N_COARSE // 2, stream=None):
+    """Returns (sel uint8 [n, 1024], conf float [n]) on the GPU."""
+    import torch
+    n = prob.shape[0]
+    sel = torch.empty((n, N_COARSE), dtype=torch.uint8, device=prob.device)
+    conf = torch.empty(n, dtype=torch.float32, device=prob.device)
+    _check(lib().cyc_select(_p(prob), n, int(topk), int(width), int(zero_bin), _p(sel), _p(conf),
+                            _stream_handle(stream)), "cyc_select")
+    return sel, conf
+
+
+def cyc_peak_labels(R, Rc, n_coarse: int = N_COARSE, zero_bin: int = N_COARSE // 2, thresh: float = 7.0,
+                    stream=None):
+    """R, Rc: complex64 CUDA tensors [T, A] -> float labels [n_coarse] on the GPU."""
+    import torch
+    lab = torch.empty(n_coarse, dtype=torch.float32, device=R.device)
+    _check(lib().cyc_peak_labels(_p(R), _p(Rc), R.shape[0], R.shape[1], int(n_coarse), int(zero_bin),
+                                 float(thresh), _p(lab), _stream_handle(stream)), "cyc_peak_labels")
+    return lab
