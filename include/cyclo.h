@@ -219,13 +219,16 @@ int cyc_batch_query(const cyc_batch* b, int32_t* kernel_cfg, int32_t* rounds, in
  * (64 Hann-windowed segments of 1024, averaged |FFT|^2) of x, x^2 and |x|^2,
  * shifted to frequencies -1/2 + m/1024, log, standardised per channel.
  * Layout of a feature batch: float [3][n_windows][1024] (channel-major).
- * Network: 4 circular conv1d layers (64 channels, kernel 7, ReLU), then a
- * dense 65536 -> 1024 layer and a sigmoid: probability that coarse bin k
- * (cycle frequencies [-1/2 + k/1024, -1/2 + (k+1)/1024)) holds a feature.
+ * Network: 4 circular conv1d layers (64 channels, kernel 7, ReLU), then per
+ * coarse bin k the sum of a dense 65536 -> 1024 layer, a bias and a local
+ * layer (sum over channels c of Wl[c] * activation[c][position k], weights
+ * shared by all bins), and a sigmoid: probability that coarse bin k (cycle
+ * frequencies [-1/2 + k/1024, -1/2 + (k+1)/1024)) holds a feature.
  * Parameters: one FP32 vector of cyc_model_num_params() values, in the order
  * W0[64][3][7], b0[64], W1[64][64][7], b1, W2, b2, W3, b3, Wh[1024][65536],
- * bh[1024].  flags: CYC_OP_FP32 or CYC_OP_BF16 operands for every matrix
- * product (FP32 accumulation, FP32 master weights and AdamW moments).
+ * bh[1024], Wl[64].  flags: CYC_OP_FP32 or CYC_OP_BF16 operands for every
+ * matrix product (FP32 accumulation, FP32 master weights and AdamW moments;
+ * the local layer is FP32 in both).
  * max_batch bounds n_windows of every call (activations are allocated at
  * creation).  All d_* pointers are device memory.  Errors: CYC_EINVAL,
  * CYC_EUNSUPPORTED (other precisions), CYC_ENOMEM, CYC_EDEVICE.
@@ -261,8 +264,13 @@ int cyc_select(const float* d_prob, int32_t n, int32_t topk, int32_t width, int3
  * Labels from full-grid tables: d_R, d_Rc complex64 [n_lag][n_alpha] of one
  * window, n_alpha = n_coarse * (fine bins per coarse bin).  Coarse bin c is 1
  * if some fine bin of it has |R| > thresh * sigma_t at some lag t in either
- * table, sigma_t = mean over alpha of |R[t][.]| / sqrt(pi/2) (the Rayleigh
- * scale of noise-only cells); the non-conjugate table is ignored in zero_bin.
+ * table.  sigma is local: for fine bins of coarse bin c at lag t it is the
+ * median of |R[t][.]| over the fine bins of coarse bins c-1, c, c+1 (circular)
+ * divided by sqrt(2 ln 2), the Rayleigh scale of noise-only cells (an even
+ * count takes the mean of the two middle magnitudes).  The non-conjugate
+ * table is ignored in zero_bin (-1 for none).  Magnitudes and the threshold
+ * are FP64.  Requires 3 * n_alpha / n_coarse <= 1024 and n_lag <= 65535.
+ * A workspace of 16 * n_lag * n_coarse bytes is allocated stream-ordered.
  */
 int cyc_peak_labels(const void* d_R, const void* d_Rc, int32_t n_lag, int32_t n_alpha,
                     int32_t n_coarse, int32_t zero_bin, float thresh, float* d_labels, void* stream);

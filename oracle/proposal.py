@@ -12,8 +12,10 @@ learned form of that coarse stage:
 * features: Welch spectra (Hann window, non-overlapping segments, averaged
   squared magnitude) of x, x^2 and |x|^2, shifted to [-1/2, 1/2), log, then
   standardised per channel;
-* the network: circular 1-D convolutions with ReLU, then a dense layer over
-  the flattened channels x positions and a sigmoid per coarse bin;
+* the network: circular 1-D convolutions with ReLU, then per coarse bin the
+  sum of a dense layer over the flattened channels x positions and a local
+  layer (one weight per channel, shared by all bins) over the channels at
+  that bin's position, and a sigmoid;
 * binary cross-entropy loss (mean over windows and bins), its gradients by
   the chain rule, and one AdamW step;
 * labels: coarse bins holding a peak of the full-grid tables;
@@ -58,6 +60,7 @@ def init_params(rng, C_in=3, C=64, K=7, L=1024, n_out=1024, n_conv=4):
         cin = C
     p["Wh"] = rng.standard_normal((n_out, C * L)) * np.sqrt(1.0 / (C * L))
     p["bh"] = np.zeros(n_out)
+    p["Wl"] = rng.standard_normal(C) * np.sqrt(1.0 / C)
     return p
 
 
@@ -102,6 +105,8 @@ def forward(p, X, n_conv=4):
         acts.append(a)
     h = a.reshape(a.shape[0], -1)           # h[n, c*L + t] = a[n, c, t]
     z = h @ p["Wh"].T + p["bh"][None, :]
+    # local layer: output bin j reads position j (requires n_out == L)
+    z = z + np.einsum("c,ncj->nj", p["Wl"], a)
     return z, dict(acts=acts, pre=pre, h=h)
 
 
@@ -116,8 +121,9 @@ def backward(p, cache, z, y, n_conv=4):
     dz = (sigmoid(z) - y) / z.size
     g["Wh"] = dz.T @ cache["h"]
     g["bh"] = dz.sum(axis=0)
+    g["Wl"] = np.einsum("nj,ncj->c", dz, cache["acts"][-1])
     dh = dz @ p["Wh"]
-    da = dh.reshape(cache["acts"][-1].shape)
+    da = dh.reshape(cache["acts"][-1].shape) + p["Wl"][None, :, None] * dz[:, None, :]
     for i in reversed(range(n_conv)):
         du = da * (cache["pre"][i] > 0)
         dx, g[f"W{i}"], g[f"b{i}"] = conv_circ_backward(cache["acts"][i], p[f"W{i}"], du)
@@ -138,15 +144,31 @@ def adamw_step(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, wd=1e-2):
 # ----------------------------------------------------------------------------- labels and selection
 
 
-def peak_cells(R, thresh: float = 7.0):
-    """|R[t, a]| / sigma_t > thresh with sigma_t = mean_a |R[t, a]| / sqrt(pi/2).
+def local_sigma(m, n_coarse: int):
+    """Noise scale per (lag, coarse bin) from magnitudes m [T, A].
 
-    For noise-only cells |R| is Rayleigh distributed with mean sigma*sqrt(pi/2);
-    a few feature cells among many alphas move the mean very little.
+    sigma[t, c] = median of m[t, a] over the fine bins a of coarse bins c-1, c
+    and c+1 (circular, since alpha is 1-periodic) divided by sqrt(2 ln 2): for
+    noise-only cells |R| is Rayleigh distributed with scale sigma, whose median
+    is sigma * sqrt(2 ln 2) (about 1.1774 sigma).  The estimate is local
+    because the self-noise of a modulated signal is strong in band and weak
+    out of band; a line feature occupies a few of the 3 * A / n_coarse cells
+    and does not move the median.  An even count takes the mean of the two
+    middle values.
     """
+    T, A = m.shape
+    per = A // n_coarse
+    blocks = m.reshape(T, n_coarse, per)
+    win = np.concatenate([np.roll(blocks, 1, axis=1), blocks, np.roll(blocks, -1, axis=1)], axis=2)
+    return np.median(win, axis=2) / np.sqrt(2.0 * np.log(2.0))
+
+
+def peak_cells(R, n_coarse: int, thresh: float = 7.0):
+    """|R[t, a]| > thresh * sigma[t, coarse bin of a] (a local median CFAR test)."""
     m = np.abs(R)
-    sigma = np.mean(m, axis=1, keepdims=True) / np.sqrt(np.pi / 2.0)
-    return m > thresh * np.maximum(sigma, 1e-300)
+    per = R.shape[1] // n_coarse
+    sigma = np.repeat(local_sigma(m, n_coarse), per, axis=1)
+    return m > thresh * sigma
 
 
 def coarse_labels(R, Rc, n_coarse: int, zero_bin: int, thresh: float = 7.0) -> np.ndarray:
@@ -157,9 +179,10 @@ def coarse_labels(R, Rc, n_coarse: int, zero_bin: int, thresh: float = 7.0) -> n
     """
     A = R.shape[1]
     per = A // n_coarse
-    pk = peak_cells(R, thresh).any(axis=0).reshape(n_coarse, per).any(axis=1)
-    pkc = peak_cells(Rc, thresh).any(axis=0).reshape(n_coarse, per).any(axis=1)
-    pk[zero_bin] = False
+    pk = peak_cells(R, n_coarse, thresh).any(axis=0).reshape(n_coarse, per).any(axis=1)
+    pkc = peak_cells(Rc, n_coarse, thresh).any(axis=0).reshape(n_coarse, per).any(axis=1)
+    if zero_bin is not None and zero_bin >= 0:   # a negative bin means none is excluded
+        pk[zero_bin] = False
     return (pk | pkc).astype(np.float64)
 
 

@@ -25,6 +25,8 @@ namespace cyclo {
 namespace nn {
 
 constexpr int CIN = 3, CH = 64, KW = 7, LEN = 1024, NOUT = 1024, NCONV = 4, WIN = 65536, NSEG = 64;
+constexpr int LABEL_WIN = 1024;  // largest label window (3 coarse bins of fine bins)
+static_assert(NOUT == LEN, "the local layer maps spectral position j to coarse bin j");
 constexpr int HDIM = CH * LEN;  // flattened head input
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -44,11 +46,13 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
 // op(B)[k][n] = TB ? B[n*ldb+k] : B[k*ldb+n].  128x128 tiles, 32-deep K steps,
 // four waves of 64x64 (2x2 blocks of 32x32 MFMA).  Tiles are staged in LDS
 // k-contiguous (FP32) and rounded to BF16 while forming fragments in BF16 mode.
+// Split K: block z covers k in [z*kchunk, (z+1)*kchunk) and, when part is set,
+// writes its partial product to part[z][M][N] for splitk_reduce_kernel.
 template <int PREC, int TA, int TB>
 __global__ __launch_bounds__(256) void gemm_kernel(const float* __restrict__ A,
                                                    const float* __restrict__ B, float* __restrict__ C,
                                                    int M, int N, int K, int lda, int ldb, int ldc,
-                                                   int accumulate) {
+                                                   int accumulate, int kchunk, float* __restrict__ part) {
   constexpr int BM = 128, BN = 128, BK = 32, LP = BK + 4;
   __shared__ __attribute__((aligned(16))) float As[BM][LP];
   __shared__ __attribute__((aligned(16))) float Bs[BN][LP];
@@ -63,7 +67,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float* __restrict__ A,
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
     // A tile -> As[m][k]
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -79,7 +84,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float* __restrict__ A,
       }
       const int gm = m0 + mm, gk = k0 + kk;
       float v = 0.f;
-      if (gm < M && gk < K) v = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
+      if (gm < M && gk < kend) v = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
       As[mm][kk] = v;
     }
     // B tile -> Bs[n][k]
@@ -97,7 +102,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float* __restrict__ A,
       }
       const int gn = n0 + nn, gk = k0 + kk;
       float v = 0.f;
-      if (gn < N && gk < K) v = TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
+      if (gn < N && gk < kend) v = TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
       Bs[nn][kk] = v;
     }
     __syncthreads();
@@ -148,7 +153,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float* __restrict__ A,
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-        if (row < M) {
+        if (row >= M) continue;
+        if (part) {
+          part[((int64_t)blockIdx.z * M + row) * N + col] = acc[i][j][v];
+        } else {
           float* c = &C[(int64_t)row * ldc + col];
           *c = accumulate ? *c + acc[i][j][v] : acc[i][j][v];
         }
@@ -156,19 +164,50 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float* __restrict__ A,
     }
 }
 
+// C[m][n] (+)= sum_z part[z][m][n], z in increasing order
+__global__ void splitk_reduce_kernel(const float* __restrict__ part, float* __restrict__ C, int M, int N, int ldc,
+                                     int S, int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)M * N) return;
+  const int64_t m = i / N, n = i % N;
+  float s = 0.f;
+  for (int z = 0; z < S; ++z) s += part[(int64_t)z * M * N + i];
+  float* c = &C[m * ldc + n];
+  *c = accumulate ? *c + s : s;
+}
+
+// Launches a GEMM; with fewer output tiles than about two per compute unit the
+// K range is split over grid.z (partials in ws, at most ws_cap floats) and
+// reduced in a second pass.
 hipError_t gemm(int prec, bool ta, bool tb, const float* A, const float* B, float* C, int M, int N, int K,
-                int lda, int ldb, int ldc, bool accumulate, hipStream_t st) {
-  const dim3 grid((N + 127) / 128, (M + 127) / 128);
+                int lda, int ldb, int ldc, bool accumulate, hipStream_t st, float* ws = nullptr,
+                int64_t ws_cap = 0) {
+  const int tiles = ((N + 127) / 128) * ((M + 127) / 128);
+  int S = 1;
+  if (ws && tiles < 512) {
+    S = std::min((512 + tiles - 1) / tiles, K / 512);
+    while (S > 1 && (int64_t)S * M * N > ws_cap) --S;
+    S = std::max(S, 1);
+  }
+  const int kchunk = S > 1 ? ((K + S - 1) / S + 31) / 32 * 32 : K;
+  if (S > 1) S = (K + kchunk - 1) / kchunk;
+  float* part = S > 1 ? ws : nullptr;
+  const dim3 grid((N + 127) / 128, (M + 127) / 128, S);
+  bool launched = false;
 #define GEMM_CASE(P, X, Y)                                                                           \
-  if (prec == P && ta == (bool)X && tb == (bool)Y) {                                                 \
+  if (!launched && prec == P && ta == (bool)X && tb == (bool)Y) {                                    \
     hipLaunchKernelGGL((gemm_kernel<P, X, Y>), grid, dim3(256), 0, st, A, B, C, M, N, K, lda, ldb, ldc, \
-                       accumulate ? 1 : 0);                                                          \
-    return hipGetLastError();                                                                        \
+                       accumulate ? 1 : 0, kchunk, part);                                            \
+    launched = true;                                                                                 \
   }
   GEMM_CASE(0, 0, 0) GEMM_CASE(0, 0, 1) GEMM_CASE(0, 1, 0) GEMM_CASE(0, 1, 1)
   GEMM_CASE(1, 0, 0) GEMM_CASE(1, 0, 1) GEMM_CASE(1, 1, 0) GEMM_CASE(1, 1, 1)
 #undef GEMM_CASE
-  return hipErrorInvalidValue;
+  if (!launched) return hipErrorInvalidValue;
+  if (S > 1)
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)(((int64_t)M * N + 255) / 256)), dim3(256), 0, st, ws,
+                       C, M, N, ldc, S, accumulate ? 1 : 0);
+  return hipGetLastError();
 }
 
 // ----------------------------------------------------------------------------- elementwise
@@ -257,6 +296,38 @@ __global__ void head_layout_kernel(const float* src, float* dst, int nb_, int di
     dst[i] = src[ia];
   else
     dst[ia] = src[i];
+}
+
+// Local layer (NOUT == LEN): z[b][j] += sum_c Wl[c] * a[c][b*LEN + j], FP32.
+__global__ void local_head_kernel(const float* a, const float* Wl, float* z, int nb_) {
+  const int64_t BL = (int64_t)nb_ * LEN;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= BL) return;
+  float s = 0.f;
+  for (int c = 0; c < CH; ++c) s = fmaf(Wl[c], a[(int64_t)c * BL + i], s);
+  z[i] += s;
+}
+
+// dWl[c] = sum_i dz[i] * a[c][i] (one block per channel, fixed reduction order)
+__global__ void local_head_wgrad_kernel(const float* a, const float* dz, float* g, int64_t BL) {
+  __shared__ float red[256];
+  const int c = blockIdx.x;
+  float s = 0.f;
+  for (int64_t i = threadIdx.x; i < BL; i += 256) s = fmaf(dz[i], a[(int64_t)c * BL + i], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) g[c] = red[0];
+}
+
+// da[c][i] += Wl[c] * dz[i]
+__global__ void local_head_dgrad_kernel(float* da, const float* Wl, const float* dz, int64_t BL) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)CH * BL) return;
+  da[i] = fmaf(Wl[i / BL], dz[i % BL], da[i]);
 }
 
 // z += bias; prob = sigmoid(z); with labels: dz = (prob - y) * scale and
@@ -387,30 +458,61 @@ __global__ void fft_table_kernel(float2* tw) {
 
 // ----------------------------------------------------------------------------- labels and selection
 
-// sigma[tab][t] = mean_a |R_tab[t][a]| / sqrt(pi/2) (FP64 sum, fixed order)
-__global__ void table_sigma_kernel(const float2* R, const float2* Rc, int A, double* sigma) {
-  __shared__ double red[256];
-  const int t = blockIdx.x, tab = blockIdx.y;
-  const float2* row = (tab ? Rc : R) + (int64_t)t * A;
-  double s = 0.0;
-  for (int a = threadIdx.x; a < A; a += 256) {
-    const float2 v = row[a];
-    s += sqrt((double)v.x * v.x + (double)v.y * v.y);
-  }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) sigma[tab * gridDim.x + t] = red[0] / A / sqrt(M_PI / 2.0);
+// |v| in FP64 as an order-preserving key (non-negative doubles sort like their bits).
+__device__ inline unsigned long long mag_key(float2 v) {
+  return (unsigned long long)__double_as_longlong(sqrt((double)v.x * v.x + (double)v.y * v.y));
 }
 
-// label[c] = 1 if some fine bin of coarse bin c exceeds thresh*sigma at some lag
-// in either table (the non-conjugate table's zero bin excluded).
-__global__ void coarse_label_kernel(const float2* R, const float2* Rc, int T, int A, int per,
-                                    int zero_bin, float thresh, const double* sigma, float* label) {
+// sigma[(tab * T + t) * nc + c] = median of |R_tab[t][a]| over the fine bins a
+// of coarse bins c-1, c, c+1 (circular) / sqrt(2 ln 2), the local Rayleigh
+// scale of noise-only cells.  The window (3 * per <= LABEL_WIN keys) is sorted
+// in LDS by a bitonic network padded with the largest key; an even count takes
+// the mean of the two middle magnitudes.
+__global__ __launch_bounds__(256) void local_sigma_kernel(const float2* R, const float2* Rc, int T, int nc, int per,
+                                                          double* sigma) {
+  __shared__ unsigned long long key[LABEL_WIN];
+  const int c = blockIdx.x, t = blockIdx.y, tab = blockIdx.z, tid = threadIdx.x;
+  const int W = 3 * per;
+  int P = 1;
+  while (P < W) P <<= 1;
+  const float2* row = (tab ? Rc : R) + (int64_t)t * nc * per;
+  for (int i = tid; i < P; i += 256) {
+    unsigned long long k = ~0ull;
+    if (i < W) {
+      int cc = c + i / per - 1;
+      cc = cc < 0 ? cc + nc : (cc >= nc ? cc - nc : cc);
+      k = mag_key(row[(int64_t)cc * per + i % per]);
+    }
+    key[i] = k;
+  }
+  __syncthreads();
+  for (int size = 2; size <= P; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < P; i += 256) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const unsigned long long u = key[i], v = key[j];
+          if ((u > v) == ((i & size) == 0)) {
+            key[i] = v;
+            key[j] = u;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  if (tid == 0) {
+    const double lo = __longlong_as_double((long long)key[(W - 1) / 2]);
+    const double hi = __longlong_as_double((long long)key[W / 2]);
+    sigma[((int64_t)tab * T + t) * nc + c] = ((W & 1) ? lo : (lo + hi) / 2.0) / 1.1774100225154747;
+  }
+}
+
+// label[c] = 1 if some fine bin of coarse bin c exceeds thresh * sigma at some
+// lag in either table (the non-conjugate table's zero bin excluded).
+__global__ void coarse_label_kernel(const float2* R, const float2* Rc, int T, int nc, int per, int zero_bin,
+                                    float thresh, const double* sigma, float* label) {
   const int c = blockIdx.x;
+  const int64_t A = (int64_t)nc * per;
   int hit = 0;
   for (int tab = 0; tab < 2; ++tab) {
     if (tab == 0 && c == zero_bin) continue;
@@ -419,7 +521,7 @@ __global__ void coarse_label_kernel(const float2* R, const float2* Rc, int T, in
       const int t = e / per, f = e % per;
       const float2 v = Rt[(int64_t)t * A + (int64_t)c * per + f];
       const double m = sqrt((double)v.x * v.x + (double)v.y * v.y);
-      if (m > (double)thresh * sigma[tab * T + t]) hit = 1;
+      if (m > (double)thresh * sigma[((int64_t)tab * T + t) * nc + c]) hit = 1;
     }
   }
   hit = __syncthreads_or(hit);
@@ -498,7 +600,7 @@ struct cyc_model {
   int prec = 0;  // 0: FP32 operands, 1: BF16 operands
   int maxb = 0;
   int64_t np = 0;
-  int64_t offW[NCONV], offb[NCONV], offWh = 0, offbh = 0;
+  int64_t offW[NCONV], offb[NCONV], offWh = 0, offbh = 0, offWl = 0;
   float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
   int step = 0;
   float* u[NCONV] = {};  // pre-activations [CH][B*LEN]
@@ -512,6 +614,8 @@ struct cyc_model {
   float* db2 = nullptr;
   double* partial = nullptr;
   float2* tw = nullptr;
+  float* ws = nullptr;  // split-K partial products
+  int64_t ws_cap = 0;
 };
 
 namespace {
@@ -522,12 +626,12 @@ int64_t model_nparams() {
     n += (int64_t)CH * cin * KW + CH;
     cin = CH;
   }
-  return n + (int64_t)NOUT * HDIM + NOUT;
+  return n + (int64_t)NOUT * HDIM + NOUT + CH;
 }
 
 void model_free(cyc_model* m) {
   if (!m) return;
-  float* bufs[] = {m->w, m->g, m->m, m->v, m->col, m->dcol, m->hbuf, m->z, m->dz, m->da, m->db2};
+  float* bufs[] = {m->w, m->g, m->m, m->v, m->col, m->dcol, m->hbuf, m->z, m->dz, m->da, m->db2, m->ws};
   for (float* p : bufs) (void)hipFree(p);
   for (int i = 0; i < NCONV; ++i) {
     (void)hipFree(m->u[i]);
@@ -551,7 +655,7 @@ hipError_t model_forward(cyc_model* m, const float* feat, int n, hipStream_t st)
   for (int i = 0; i < NCONV; ++i) {
     hipLaunchKernelGGL(im2col_kernel, dim3(nb((int64_t)cin * KW * BL)), dim3(256), 0, st, in, m->col, cin, n);
     hipError_t e = gemm(m->prec, false, false, m->w + m->offW[i], m->col, m->u[i], CH, (int)BL, cin * KW,
-                        cin * KW, (int)BL, (int)BL, false, st);
+                        cin * KW, (int)BL, (int)BL, false, st, m->ws, m->ws_cap);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(bias_relu_kernel, dim3(nb((int64_t)CH * BL)), dim3(256), 0, st, m->u[i],
                        m->w + m->offb[i], m->a[i], CH, BL);
@@ -560,7 +664,11 @@ hipError_t model_forward(cyc_model* m, const float* feat, int n, hipStream_t st)
   }
   hipLaunchKernelGGL(head_layout_kernel, dim3(nb((int64_t)n * HDIM)), dim3(256), 0, st, m->a[NCONV - 1],
                      m->hbuf, n, 0);
-  return gemm(m->prec, false, true, m->hbuf, m->w + m->offWh, m->z, n, NOUT, HDIM, HDIM, HDIM, NOUT, false, st);
+  hipError_t e = gemm(m->prec, false, true, m->hbuf, m->w + m->offWh, m->z, n, NOUT, HDIM, HDIM, HDIM, NOUT,
+                      false, st, m->ws, m->ws_cap);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(local_head_kernel, dim3(nb(BL)), dim3(256), 0, st, m->a[NCONV - 1], m->w + m->offWl, m->z, n);
+  return hipGetLastError();
 }
 
 // Gradients of the mean BCE into m->g; loss partial sums into m->partial.
@@ -573,13 +681,19 @@ hipError_t model_backward(cyc_model* m, const float* feat, const float* labels, 
   hipLaunchKernelGGL(head_out_kernel, dim3(*nblk), dim3(256), 0, st, m->z, m->w + m->offbh, (float*)nullptr,
                      labels, m->dz, 1.f / (float)nz, m->partial, nz);
   // head
-  e = gemm(m->prec, true, false, m->dz, m->hbuf, m->g + m->offWh, NOUT, HDIM, n, NOUT, HDIM, HDIM, false, st);
+  e = gemm(m->prec, true, false, m->dz, m->hbuf, m->g + m->offWh, NOUT, HDIM, n, NOUT, HDIM, HDIM, false, st,
+           m->ws, m->ws_cap);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(colsum_kernel, dim3(nb(NOUT)), dim3(256), 0, st, m->dz, m->g + m->offbh, n, NOUT);
-  e = gemm(m->prec, false, false, m->dz, m->w + m->offWh, m->hbuf, n, HDIM, NOUT, NOUT, HDIM, HDIM, false, st);
+  e = gemm(m->prec, false, false, m->dz, m->w + m->offWh, m->hbuf, n, HDIM, NOUT, NOUT, HDIM, HDIM, false, st,
+           m->ws, m->ws_cap);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(head_layout_kernel, dim3(nb((int64_t)n * HDIM)), dim3(256), 0, st, m->hbuf, m->da, n, 1);
   const int64_t BL = (int64_t)n * LEN;
+  hipLaunchKernelGGL(local_head_wgrad_kernel, dim3(CH), dim3(256), 0, st, m->a[NCONV - 1], m->dz, m->g + m->offWl,
+                     BL);
+  hipLaunchKernelGGL(local_head_dgrad_kernel, dim3(nb((int64_t)CH * BL)), dim3(256), 0, st, m->da,
+                     m->w + m->offWl, m->dz, BL);
   for (int i = NCONV - 1; i >= 0; --i) {
     const int cin = i == 0 ? CIN : CH;
     const float* in = i == 0 ? feat : m->a[i - 1];
@@ -587,12 +701,12 @@ hipError_t model_backward(cyc_model* m, const float* feat, const float* labels, 
                        (int64_t)CH * BL);
     hipLaunchKernelGGL(im2col_kernel, dim3(nb((int64_t)cin * KW * BL)), dim3(256), 0, st, in, m->col, cin, n);
     e = gemm(m->prec, false, true, m->da, m->col, m->g + m->offW[i], CH, cin * KW, (int)BL, (int)BL, (int)BL,
-             cin * KW, false, st);
+             cin * KW, false, st, m->ws, m->ws_cap);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(rowsum_kernel, dim3(CH), dim3(256), 0, st, m->da, m->g + m->offb[i], BL);
     if (i > 0) {
       e = gemm(m->prec, true, false, m->w + m->offW[i], m->da, m->dcol, cin * KW, (int)BL, CH, cin * KW,
-               (int)BL, (int)BL, false, st);
+               (int)BL, (int)BL, false, st, m->ws, m->ws_cap);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(col2im_kernel, dim3(nb((int64_t)cin * BL)), dim3(256), 0, st, m->dcol, m->da, cin, n);
     }
@@ -638,6 +752,8 @@ int cyc_model_create(cyc_model** out, int32_t max_batch, uint32_t flags, void* s
   o += (int64_t)NOUT * HDIM;
   m->offbh = o;
   o += NOUT;
+  m->offWl = o;
+  o += CH;
   m->np = o;
   const int64_t BL = (int64_t)max_batch * LEN;
   bool ok = dal(&m->w, o) == hipSuccess && dal(&m->g, o) == hipSuccess && dal(&m->m, o) == hipSuccess &&
@@ -647,6 +763,8 @@ int cyc_model_create(cyc_model** out, int32_t max_batch, uint32_t flags, void* s
             dal(&m->z, (int64_t)max_batch * NOUT) == hipSuccess &&
             dal(&m->dz, (int64_t)max_batch * NOUT) == hipSuccess && dal(&m->da, (int64_t)CH * BL) == hipSuccess &&
             dal(&m->partial, (int64_t)nb((int64_t)max_batch * NOUT)) == hipSuccess && dal(&m->tw, LEN / 2) == hipSuccess;
+  m->ws_cap = (int64_t)1 << 24;
+  ok = ok && dal(&m->ws, m->ws_cap) == hipSuccess;
   for (int i = 0; i < NCONV && ok; ++i)
     ok = dal(&m->u[i], (int64_t)CH * BL) == hipSuccess && dal(&m->a[i], (int64_t)CH * BL) == hipSuccess;
   if (!ok) {
@@ -747,18 +865,21 @@ int cyc_select(const float* d_prob, int32_t n, int32_t topk, int32_t width, int3
 
 int cyc_peak_labels(const void* d_R, const void* d_Rc, int32_t n_lag, int32_t n_alpha, int32_t n_coarse,
                     int32_t zero_bin, float thresh, float* d_labels, void* stream) {
-  if (!d_R || !d_Rc || !d_labels || n_lag < 1 || n_alpha < 1 || n_coarse < 1 || n_alpha % n_coarse != 0 ||
-      zero_bin < -1 || zero_bin >= n_coarse || !(thresh > 0.f))
+  if (!d_R || !d_Rc || !d_labels || n_lag < 1 || n_lag > 65535 || n_alpha < 1 || n_coarse < 1 ||
+      n_alpha % n_coarse != 0 || 3 * (n_alpha / n_coarse) > LABEL_WIN || zero_bin < -1 || zero_bin >= n_coarse ||
+      !(thresh > 0.f))
     return CYC_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int per = n_alpha / n_coarse;
   double* sigma = nullptr;
-  if (hipMallocAsync(reinterpret_cast<void**>(&sigma), sizeof(double) * 2 * n_lag, st) != hipSuccess)
+  if (hipMallocAsync(reinterpret_cast<void**>(&sigma), sizeof(double) * 2 * n_lag * (size_t)n_coarse, st) !=
+      hipSuccess)
     return CYC_ENOMEM;
-  hipLaunchKernelGGL(table_sigma_kernel, dim3(n_lag, 2), dim3(256), 0, st, reinterpret_cast<const float2*>(d_R),
-                     reinterpret_cast<const float2*>(d_Rc), n_alpha, sigma);
+  hipLaunchKernelGGL(local_sigma_kernel, dim3(n_coarse, n_lag, 2), dim3(256), 0, st,
+                     reinterpret_cast<const float2*>(d_R), reinterpret_cast<const float2*>(d_Rc), n_lag, n_coarse,
+                     per, sigma);
   hipLaunchKernelGGL(coarse_label_kernel, dim3(n_coarse), dim3(256), 0, st, reinterpret_cast<const float2*>(d_R),
-                     reinterpret_cast<const float2*>(d_Rc), n_lag, n_alpha, n_alpha / n_coarse, zero_bin, thresh,
-                     sigma, d_labels);
+                     reinterpret_cast<const float2*>(d_Rc), n_lag, n_coarse, per, zero_bin, thresh, sigma, d_labels);
   const bool ok = hipGetLastError() == hipSuccess;
   (void)hipFreeAsync(sigma, st);
   return ok ? CYC_OK : CYC_EDEVICE;

@@ -422,6 +422,13 @@ class ProposalModel:
                                          _stream_handle(stream)), "cyc_model_gradients")
         return g, loss.value
 
+    def loss(self, feat, labels, stream=None) -> float:
+        """Mean BCE of the current parameters (gradients are computed, not returned)."""
+        loss = ctypes.c_double()
+        _check(lib().cyc_model_gradients(self._m, _p(feat), _p(labels), feat.shape[1], None, ctypes.byref(loss),
+                                         _stream_handle(stream)), "cyc_model_gradients")
+        return loss.value
+
     def train_step(self, feat, labels, lr: float, weight_decay: float, stream=None) -> float:
         loss = ctypes.c_double()
         _check(lib().cyc_model_train_step(self._m, _p(feat), _p(labels), feat.shape[1], float(lr),

@@ -7,7 +7,7 @@ import pytest
 from oracle import proposal as P
 
 
-def _tiny(seed=0, N=3, C_in=3, C=4, K=7, L=16, n_out=5, n_conv=2):
+def _tiny(seed=0, N=3, C_in=3, C=4, K=7, L=16, n_out=16, n_conv=2):
     rng = np.random.default_rng(seed)
     p = P.init_params(rng, C_in=C_in, C=C, K=K, L=L, n_out=n_out, n_conv=n_conv)
     for k in p:
@@ -50,6 +50,18 @@ def test_gradients_by_central_differences():
             fd = (lp - lm) / (2 * h)
             an = g[k].reshape(-1)[idx]
             assert abs(fd - an) <= 1e-6 * max(1e-4, abs(fd)) + 1e-9, (k, idx, fd, an)
+
+
+def test_local_layer_reads_the_bins_own_position():
+    # with the dense layer zeroed, logit j is b_j + sum_c Wl[c] * relu(last conv)[c, j]
+    p, X, _ = _tiny(n_conv=2)
+    p["Wh"][:] = 0.0
+    z, cache = P.forward(p, X, 2)
+    a = cache["acts"][-1]
+    for n in range(X.shape[0]):
+        for j in range(16):
+            ref = p["bh"][j] + sum(p["Wl"][c] * a[n, c, j] for c in range(4))
+            assert abs(z[n, j] - ref) < 1e-12
 
 
 def test_adamw_first_steps_scalar():
@@ -98,3 +110,45 @@ def test_labels_exclude_power_bin():
     Rc[0, 250] = 1.0         # a conjugate feature in coarse bin 15
     lab = P.coarse_labels(R, Rc, n_coarse, zero_bin=8)
     assert list(np.nonzero(lab)[0]) == [2, 15]
+
+
+def test_peak_rule_uses_the_rayleigh_median():
+    # sigma = median / sqrt(2 ln 2); threshold 7 sigma.  With 3 coarse bins every
+    # window holds the whole row.
+    c = np.sqrt(2 * np.log(2))
+    # 11 ones and an 8: median 1 -> threshold 7/c = 5.95 flags the 8
+    # (the mean 1.58 would give 9.4 and flag nothing).
+    row = np.array([1.0] * 11 + [8.0])
+    assert list(np.nonzero(P.peak_cells(row[None, :], 3)[0])[0]) == [11]
+    # even count: the mean of the two middle values (1.5) -> threshold 8.92;
+    # the upper middle (2) would miss the 10, the lower middle (1) would flag the 7.
+    base = [0.5] * 5 + [1.0, 2.0] + [3.0] * 4
+    pk = P.peak_cells(np.array([base + [10.0], base + [7.0]]), 3)
+    assert pk[0].tolist() == [False] * 11 + [True]
+    assert not pk[1].any()
+    assert abs(7 * 1.5 / c - 8.9177) < 1e-3
+
+
+def test_peak_rule_noise_scale_is_local():
+    # 8 coarse bins of 4: a pedestal of 10 over bins 0..3, 1 elsewhere.  The
+    # window of bin c is bins c-1..c+1 (circular).
+    row = np.ones(32)
+    row[:16] = 10.0
+    row[5] = 30.0      # bin 1: local median 10 -> threshold 59 -> no peak
+    row[26] = 6.0      # bin 6: local median 1 -> threshold 5.95 -> peak
+    pk = P.peak_cells(row[None, :], 8)[0]
+    assert list(np.nonzero(pk)[0]) == [26]
+    # a global median (5.5 -> threshold 32.7) would flag neither; the window
+    # edges (bins 3, 4 and 7, 0) raise no peak at the pedestal's steps
+    sig = P.local_sigma(row[None, :], 8)[0] * np.sqrt(2 * np.log(2))
+    assert sig.tolist() == [10, 10, 10, 10, 1, 1, 1, 1]
+
+
+def test_peak_rule_noise_scale_is_rayleigh():
+    # complex Gaussian noise of scale s: |R| is Rayleigh(s); the estimate recovers s,
+    # so the false-alarm rate at 3 sigma is exp(-9/2)
+    rng = np.random.default_rng(7)
+    s = 0.37
+    R = s * (rng.standard_normal((2, 200000)) + 1j * rng.standard_normal((2, 200000)))
+    frac = P.peak_cells(R, 1000, thresh=3.0).mean()
+    assert abs(frac - np.exp(-4.5)) < 0.1 * np.exp(-4.5)
