@@ -7,7 +7,11 @@ the timed region.  Default workload: QPSK with a root-raised-cosine pulse
 complex64 samples pushed in 256 blocks of 65536, lags 0..127, 4096 cycle
 frequencies alpha_k = -1/2 + k/4096, FP32 operands.
 
-Output: one JSON line (metric, value, ..., roofline, cpu_baseline).
+Extra forms in the same line: the 512-stream batch form and the learned
+proposal (trained in the run on 8192 windows, then timed against the full fine
+grid on held-out windows).
+
+Output: one JSON line (metric, value, ..., roofline, cpu_baseline, forms).
 value = (alpha, tau)*samples per second = A * T * N_used / seconds per step.
 """
 from __future__ import annotations
@@ -182,6 +186,35 @@ def run_batch(bw, prec: str, steps: int, warmup: int, compare_single: bool = Fal
     return out
 
 
+def run_proposal(n_train: int, pool):
+    """Learned proposal trained in this run, then timed against the full fine grid.
+
+    Windows of 65536 mixed-modulation samples, labels from the full-grid
+    estimator (65536 alphas, lags 0..63, BF16), BF16 training with FP32
+    master weights; the fallback threshold is tuned on validation windows for
+    a 2 % miss rate; timing on 256 held-out windows.
+    """
+    from paper_2405_16911_amd import proposal
+    r = proposal.run(n_train=n_train, n_val=512, n_test=256, epochs=20, batch=64, lr=1e-3, wd=0.1, seed=5,
+                     target_miss=0.02, log=lambda m: print(m, file=sys.stderr, flush=True), pool=pool)
+    ev, sp = r["eval"], r["speed"]
+    return dict(workload="mixed_gmsk_psk_ofdm_window65536_fine65536_T64",
+                metric="learned-proposal vs full-grid speedup at equal error",
+                speedup=sp["speedup"], miss_rate=ev["trained"]["miss_rate"],
+                fallback_rate=ev["trained"]["fallback_rate"], theta=r["theta"],
+                speedup_no_fallback=sp["speedup_no_fallback"],
+                miss_rate_no_fallback=ev["trained"]["miss_rate_without_fallback"],
+                miss_rate_untrained=ev["untrained"]["miss_rate_without_fallback"],
+                miss_rate_heuristic=ev["heuristic"]["miss_rate_without_fallback"],
+                max_rel_diff_vs_full_grid=sp["max_rel_diff_vs_full_grid"],
+                evaluated_alphas_per_window=sp["evaluated_alphas_per_window"],
+                full_grid_ms_per_window=1e3 * sp["full_grid_s"] / sp["windows"],
+                proposal_ms_per_window=1e3 * sp["proposal_path_s"] / sp["windows"],
+                theta_curve=r["theta_curve"], train=r["train"], labelling_s=r["labelling_s"],
+                positives_per_window=r["positives_per_window"],
+                windows=dict(train=n_train, val=512, test=256))
+
+
 def copy_calibration(nbytes: int = 256 << 20, reps: int = 5):
     """A plain copy kernel of known size: reads and writes nbytes per launch."""
     import torch
@@ -206,8 +239,10 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=1 << 21)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--forms", default="batch",
-                    help="extra forms measured after the main workload: 'batch' or ''")
+    ap.add_argument("--forms", default="batch,proposal",
+                    help="extra forms measured after the main workload: any of 'batch', 'proposal' ('' for none)")
+    ap.add_argument("--proposal-train", type=int, default=8192,
+                    help="training windows of the learned proposal trained inside the run")
     ap.add_argument("--batch-streams", type=int, default=512)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain elementwise copy of 256 MiB (HBM counter calibration)")
@@ -220,6 +255,12 @@ def main():
                                    "a design note, not an implemented path", "n_gpus": args.gpus}))
         raise SystemExit(2)
 
+    forms_wanted = [f for f in args.forms.split(",") if f]
+    pool = None
+    if "proposal" in forms_wanted:
+        from multiprocessing import Pool
+        # window generators, forked before anything in this process touches the GPU
+        pool = Pool(max(1, min(16, os.cpu_count() or 1)))
     wl = workload(args.workload)
     main_run = run_gpu(wl, args.precision, args.split, args.steps, args.warmup, not args.no_autotune)
     prof = main_run["prof"]
@@ -260,13 +301,16 @@ def main():
         "variants": variants,
     }
     forms = {}
-    if "batch" in args.forms.split(","):
+    if "batch" in forms_wanted:
         bw = batch_workload(args.batch_streams)
         forms["batch"] = dict(workload=bw["desc"], n_streams=len(bw["xs"]),
                               n_samples=int(sum(x.size for x in bw["xs"])),
                               runs=[run_batch(bw, "bf16", 3, 1, compare_single=True),
                                     run_batch(bw, "f32", 2, 1)])
         del bw
+    if "proposal" in forms_wanted:
+        forms["proposal"] = run_proposal(args.proposal_train, pool)
+        pool.close()
     if forms:
         out["forms"] = forms
     if not args.no_cpu_baseline:

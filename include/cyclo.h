@@ -48,7 +48,9 @@ extern "C" {
 
 /* ---- flags for cyc_create ------------------------------------------------ */
 /* Operand precision of the matrix-core contraction (accumulation is always
- * FP32 within a chunk and FP64 across chunks; the alpha*n reduction is FP64). */
+ * FP32 within a chunk and FP64 across chunks; the alpha*n reduction is FP64).
+ * A chunk is 4096 products (the environment variable CYC_CHUNK, read at
+ * creation, overrides it; batches default to 16384 for BF16/FP16). */
 #define CYC_OP_FP32   0x0u   /* FP32 operands (default)                       */
 #define CYC_OP_BF16   0x1u   /* BF16 operands                                 */
 #define CYC_OP_FP16   0x2u   /* FP16 operands                                 */

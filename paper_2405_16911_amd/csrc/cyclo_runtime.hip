@@ -262,6 +262,10 @@ int cyc_create(cyc_state** out, const double* alphas_host, int32_t n_alpha, int3
   int ncfg = 0;
   const KernelCfg& cfg = kernel_cfgs(&ncfg)[s->cfg];
   s->KS = cfg.ks;
+  // Products per FP32-accumulated chunk.  A push's work is split over
+  // (alpha tiles x chunks), so a single stream keeps 4096 for every operand
+  // precision; batches take longer 16-bit chunks because their streams
+  // supply the parallelism.
   int64_t kc = env_i64("CYC_CHUNK", 4096);
   kc = std::max<int64_t>(cfg.ks, std::min<int64_t>(kc, 1 << 20));
   kc = (kc / cfg.ks) * cfg.ks;

@@ -208,7 +208,7 @@ def dataset(model, fg: FullGrid, seed: int, first: int, n: int, keep_windows: bo
     return feat, lab, (torch.cat(wins) if keep_windows else None)
 
 
-def run(n_train=4096, n_val=512, n_test=512, epochs=20, batch=256, lr=1e-3, wd=1e-2, seed=5,
+def run(n_train=4096, n_val=512, n_test=512, epochs=20, batch=64, lr=1e-3, wd=0.1, seed=5,
         target_miss=0.01, log=print, pool=None):
     import torch
     t0 = time.time()
@@ -361,16 +361,18 @@ if __name__ == "__main__":
     ap.add_argument("--n-val", type=int, default=512)
     ap.add_argument("--n-test", type=int, default=512)
     ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--out", default="")
     ap.add_argument("--workers", type=int, default=16)
-    ap.add_argument("--wd", type=float, default=1e-2)
+    ap.add_argument("--wd", type=float, default=0.1)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--target-miss", type=float, default=0.01)
     a = ap.parse_args()
     import os
     # forked before anything touches the GPU
     with Pool(max(1, min(a.workers, os.cpu_count() or 1))) as pool:
-        r = run(a.n_train, a.n_val, a.n_test, a.epochs, lr=a.lr, wd=a.wd, target_miss=a.target_miss, pool=pool)
+        r = run(a.n_train, a.n_val, a.n_test, a.epochs, batch=a.batch, lr=a.lr, wd=a.wd,
+                target_miss=a.target_miss, pool=pool)
     s = json.dumps(r, indent=1)
     print(s)
     if a.out:

@@ -88,8 +88,12 @@ def test_batch_matches_oracle_and_single_states(cy, flags):
         sc = scale_per_lag(x, T)[:, None]
         e = max(np.max(np.abs(Rs[s] - Ro) / sc), np.max(np.abs(Rcs[s] - Rco) / sc))
         assert e <= TOL[flags], (s, e)
-        # single state, same samples, the batch's kernel configuration
-        st = cy.CyclicStream(al, T, flags)
+        # single state, same samples, the batch's kernel configuration and chunk
+        # length (16-bit operands: 16384 products per chunk in a batch, 4096 in a
+        # single state by default)
+        chunk = 4096 if flags == 0 else 16384
+        st = _with_env({"CYC_CHUNK": chunk}, lambda: cy.CyclicStream(al, T, flags))
+        assert st.query()["chunk"] == chunk
         st.set_kernel_cfg(qs[-1]["kernel_cfg"])
         st.push(torch.from_numpy(np.ascontiguousarray(x)).to("cuda"))
         R1, Rc1, n1 = st.read()
