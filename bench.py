@@ -36,6 +36,31 @@ PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "f16": 2500.0}
 PREC_FLAGS = {"f32": 0x0, "bf16": 0x1, "f16": 0x2}
 
 
+HBM_PROFILE = os.path.join(ROOT, "profiles", "contract_qpsk_rrc_2p24_hbm_counters.txt")
+KERNEL_SOURCES = {name: os.path.join(ROOT, "paper_2405_16911_amd", "csrc", name)
+                  for name in ("cyclo_kernels.hip", "cyclo_internal.h")}
+
+
+def profiled_traffic(cfg_name: str):
+    """HBM bytes per launch of configuration cfg_name on the default record, from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary; None when the kernel sources
+    have changed since the counters were taken or the configuration was not profiled."""
+    import hashlib
+    if not os.path.exists(HBM_PROFILE):
+        return None
+    digests, traffic = {}, None
+    for line in open(HBM_PROFILE):
+        f = line.split()
+        if len(f) == 3 and f[0] == "source_sha256":
+            digests[f[1]] = f[2]
+        elif len(f) == 7 and f[0] == "cfg" and f[1] == cfg_name:
+            traffic = float(f[6])
+    for name, path in KERNEL_SOURCES.items():
+        if digests.get(name) != hashlib.sha256(open(path, "rb").read()).hexdigest():
+            return None
+    return traffic
+
+
 def workload(name: str):
     from paper_2405_16911_amd import siggen
     if name == "qpsk_rrc_2p24":
@@ -47,6 +72,17 @@ def workload(name: str):
         return dict(x=x, T=32, alphas=np.arange(128) / 128.0, block=32768,
                     desc="gmsk_L32768_T32_A128_push32768")
     raise SystemExit(f"unknown workload {name}")
+
+
+def algorithmic_bytes(wl, q, prof) -> float:
+    """Bytes a contraction launch must move: its samples, the twiddle tables of its
+    alphas (low table [A][KS], high table [A][Kc/KS], complex64) and its FP32 complex
+    chunk partials [2][T][A] per chunk (products per launch from the profiled work)."""
+    import re
+    T, A, Kc = wl["T"], wl["alphas"].size, q["chunk"]
+    KS = int(re.search(r"_k(\d+)", q["kernel_cfg_name"]).group(1))
+    prods = prof["work"] / max(1, prof["launches"]) / (T * A)
+    return (prods + T) * 8 + A * (KS + Kc // KS) * 8 + prods / Kc * 2 * T * A * 8
 
 
 def run_gpu(wl, prec: str, split: bool, steps: int, warmup: int, autotune: bool = True):
@@ -294,7 +330,11 @@ def main():
                    "chunk": main_run["query"]["chunk"], "kernel_cfg": main_run["query"]["kernel_cfg_name"],
                    "autotuned": main_run["tuned"] is not None},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": (profiled_traffic(main_run["query"]["kernel_cfg_name"])
+                                 if args.workload == "qpsk_rrc_2p24" else None),
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 counters scaled by a copy kernel)",
+                     "algorithmic_bytes_per_launch": algorithmic_bytes(wl, main_run["query"], prof),
                      "kernel": "contract (chunk contraction)", "kernel_ms_avg": kernel_ms,
                      "launches": prof["launches"], "flops_per_launch": FLOPS_PER_TRIPLE * prof["work"]
                      / max(1, prof["launches"])},
