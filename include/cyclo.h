@@ -263,6 +263,24 @@ int cyc_model_train_step(cyc_model* m, const float* d_feat, const float* d_label
 int cyc_select(const float* d_prob, int32_t n, int32_t topk, int32_t width, int32_t zero_bin,
                uint8_t* d_sel, float* d_conf, void* stream);
 /*
+ * The whole coarse stage in one call, for n_windows (<= max_batch) windows of
+ * 65536 complex64 samples at d_x (contiguous): spectra, network, selection as
+ * cyc_select (topk, width, zero_bin), then per window
+ *   d_bins     int32 [n_windows][1024]: the selected coarse bins in ascending
+ *              order, -1 after the last; coarse bin k holds the fine cycle
+ *              frequencies -1/2 + (64 k + f)/65536, f = 0..63;
+ *   d_n_bins   int32 [n_windows]: the number of selected bins;
+ *   d_conf     float [n_windows]: 1 - the largest probability left out;
+ *   d_fallback uint8 [n_windows]: 1 when conf < theta (evaluate the full grid).
+ * The exact estimator then runs on those cycle frequencies (cyc_create or
+ * cyc_batch_create).  Uses the model's own scratch buffers: calls on one model
+ * are serialised by the caller.  Errors: CYC_EINVAL (NULL, sizes, NaN theta),
+ * CYC_EDEVICE.
+ */
+int cyc_propose(cyc_model* m, const void* d_x, int32_t n_windows, int32_t topk, int32_t width,
+                int32_t zero_bin, float theta, int32_t* d_bins, int32_t* d_n_bins, float* d_conf,
+                uint8_t* d_fallback, void* stream);
+/*
  * Labels from full-grid tables: d_R, d_Rc complex64 [n_lag][n_alpha] of one
  * window, n_alpha = n_coarse * (fine bins per coarse bin).  Coarse bin c is 1
  * if some fine bin of it has |R| > thresh * sigma_t at some lag t in either

@@ -154,24 +154,29 @@ __device__ __forceinline__ void store_tiles(const ContractArgs& a, const TileId&
 // The global loads for step ks+2 (and its twiddle-table entry) are issued
 // before the matrix-core work of step ks and written to LDS after it, so their
 // latency is hidden.  Loads are bounds-checked, so the steady-state loop can
-// stage a window past the last step without branching.
+// stage a window past the last step without branching.  Every lane issues its
+// load unconditionally from a valid address (the start of the pending buffer
+// when its sample does not exist) and the validity mask is applied when the
+// value is written to LDS: a load inside a divergent branch would make the
+// compiler wait for it at the branch's join, right after issuing it.
 template <int NT, int XW, int KS>
 struct Stager {
   static constexpr int N = XW + KS;
   static constexpr int R = (N + NT - 1) / NT;
   float2 r[R];
+  bool ok[R];
   float2 hv;
   __device__ __forceinline__ void load(const VSrc& v, int64_t s0, int tau0, int64_t yend,
                                        const float2* hp, int tid) {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int idx = tid + i * NT;
-      if (idx < XW) {
-        r[i] = vload(v, s0 + tau0 + idx);
-      } else if (idx < N) {
-        const int64_t g = s0 + (idx - XW);
-        r[i] = g < yend ? vload(v, g) : make_float2(0.f, 0.f);
-      }
+      const bool hank = idx < XW;
+      const int64_t g = hank ? s0 + tau0 + idx : s0 + (idx - XW);
+      const bool valid = idx < N && g < v.n_avail && (hank || g < yend);
+      const float2* p = valid ? (g < v.n_pend ? v.pend + g : v.xin + (g - v.n_pend)) : v.pend;
+      r[i] = *p;
+      ok[i] = valid;
     }
     hv = *hp;
   }
@@ -179,10 +184,11 @@ struct Stager {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int idx = tid + i * NT;
+      const float2 val = ok[i] ? r[i] : make_float2(0.f, 0.f);
       if (idx < XW)
-        Xh[idx] = r[i];
+        Xh[idx] = val;
       else if (idx < N)
-        Xy[idx - XW] = r[i];
+        Xy[idx - XW] = val;
     }
   }
 };
@@ -384,13 +390,14 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
   const float2* Hrow = a.H + (int64_t)(aval ? galpha : 0) * tl.nsteps;
   auto hptr = [&](int ks) { return Hrow + min(ks, tl.nsteps - 1); };
 
-  int zoff[WM];
-#pragma unroll
-  for (int rb = 0; rb < WM; ++rb) {
-    const int R = (wm * WM + rb) * 32 + l32;
+  // Word offset of this lane's Hankel fragment for the wave's first row block
+  // (row R = 2 lag + cr, four samples from lag + 4h, in copy (cr, lag + 4h mod 4)).
+  int zoff0;
+  {
+    const int R = wm * WM * 32 + l32;
     const int p0 = (R >> 1) + 4 * h;
     const int sh = p0 & 3;
-    zoff[rb] = (R & 1) * CO + sh * ZP + (p0 - sh);
+    zoff0 = (R & 1) * CO + sh * ZP + (p0 - sh);
   }
 
   auto produce = [&](int buf, float2 hv) {
@@ -442,14 +449,21 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
     for (int k = 0; k < WN; ++k)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][k][v] = 0.f;
+  // Hankel fragments: row block rb at K block kb reads word zoff0 + 16 rb + 8 kb
+  // (the block's lags are 16 further on, and 16 = 0 mod 4 keeps the copy), so
+  // block rb + 1 at kb holds the same values as block rb at kb + 2.  Each
+  // distinct fragment of a step is read from LDS once: 2 (WM - 1) + KS / 8
+  // reads instead of WM * KS / 8.
+  constexpr int NAF = 2 * (WM - 1) + KS / 8;
   auto mfma_step = [&](int buf) {
-    const uint32_t* zb = &Zs[buf][0];
+    const uint32_t* zb = &Zs[buf][0] + zoff0;
+    uint4 af[NAF];
+#pragma unroll
+    for (int o = 0; o < NAF; ++o) af[o] = *reinterpret_cast<const uint4*>(zb + 8 * o);
 #pragma unroll
     for (int kb = 0; kb < KS / 8; ++kb) {
       const int j0 = kb * 8;
-      uint4 af[WM], bf[NB][WN];
-#pragma unroll
-      for (int rb = 0; rb < WM; ++rb) af[rb] = *reinterpret_cast<const uint4*>(zb + zoff[rb] + j0);
+      uint4 bf[NB][WN];
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -460,8 +474,8 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
       for (int rb = 0; rb < WM; ++rb)
 #pragma unroll
         for (int cb = 0; cb < WN; ++cb) {
-          acc[rb][cb] = O::mfma(af[rb], bf[0][cb], acc[rb][cb]);
-          if (SPLIT) acc[rb][cb] = O::mfma(af[rb], bf[NB - 1][cb], acc[rb][cb]);
+          acc[rb][cb] = O::mfma(af[2 * rb + kb], bf[0][cb], acc[rb][cb]);
+          if (SPLIT) acc[rb][cb] = O::mfma(af[2 * rb + kb], bf[NB - 1][cb], acc[rb][cb]);
         }
     }
   };
@@ -884,6 +898,8 @@ static const KernelCfg g_cfgs[] = {
     CFG_16_ALL(128, 128, 2, 2, 32, 1),
     CFG_16_ALL(64, 64, 2, 2, 32, 0),
     CFG_RG_ALL(8, 1, 32),
+    CFG_16_ALL(128, 64, 2, 2, 32, 1),
+    CFG_16_ALL(128, 64, 2, 2, 32, 0),
 };
 
 const KernelCfg* kernel_cfgs(int* n) {

@@ -588,6 +588,41 @@ __global__ __launch_bounds__(256) void select_kernel(const float* prob, int n, i
   if (tid == 0) conf[w] = 1.f - rv[0];
 }
 
+// Per window: the selected coarse bins in ascending order (bins[w][0 .. n)),
+// -1 after them, their count, and the fallback flag conf < theta.
+__global__ __launch_bounds__(256) void compact_bins_kernel(const uint8_t* sel, const float* conf, float theta,
+                                                           int32_t* bins, int32_t* n_bins, uint8_t* fallback) {
+  __shared__ int cnt[256];
+  const int w = blockIdx.x, tid = threadIdx.x;
+  constexpr int PER = NOUT / 256;
+  const uint8_t* sw = sel + (int64_t)w * NOUT;
+  int c = 0;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) c += sw[tid * PER + k] ? 1 : 0;
+  cnt[tid] = c;
+  __syncthreads();
+  // inclusive scan over the 256 counts (Hillis-Steele, fixed order)
+  for (int off = 1; off < 256; off <<= 1) {
+    const int v = tid >= off ? cnt[tid - off] : 0;
+    __syncthreads();
+    cnt[tid] += v;
+    __syncthreads();
+  }
+  const int total = cnt[255];
+  int pos = cnt[tid] - c;
+  int32_t* bw = bins + (int64_t)w * NOUT;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int b = tid * PER + k;
+    if (sw[b]) bw[pos++] = b;
+  }
+  for (int i = total + tid; i < NOUT; i += 256) bw[i] = -1;
+  if (tid == 0) {
+    n_bins[w] = total;
+    fallback[w] = conf[w] < theta ? 1 : 0;
+  }
+}
+
 }  // namespace nn
 }  // namespace cyclo
 
@@ -616,6 +651,9 @@ struct cyc_model {
   float2* tw = nullptr;
   float* ws = nullptr;  // split-K partial products
   int64_t ws_cap = 0;
+  float* pfeat = nullptr;    // cyc_propose: features [CIN][B][LEN]
+  float* pprob = nullptr;    // cyc_propose: probabilities [B][NOUT]
+  uint8_t* psel = nullptr;   // cyc_propose: selection [B][NOUT]
 };
 
 namespace {
@@ -631,7 +669,8 @@ int64_t model_nparams() {
 
 void model_free(cyc_model* m) {
   if (!m) return;
-  float* bufs[] = {m->w, m->g, m->m, m->v, m->col, m->dcol, m->hbuf, m->z, m->dz, m->da, m->db2, m->ws};
+  float* bufs[] = {m->w,  m->g, m->m,  m->v,  m->col, m->dcol,  m->hbuf,
+                   m->z,  m->dz, m->da, m->db2, m->ws, m->pfeat, m->pprob};
   for (float* p : bufs) (void)hipFree(p);
   for (int i = 0; i < NCONV; ++i) {
     (void)hipFree(m->u[i]);
@@ -639,6 +678,7 @@ void model_free(cyc_model* m) {
   }
   (void)hipFree(m->partial);
   (void)hipFree(m->tw);
+  (void)hipFree(m->psel);
   delete m;
 }
 
@@ -764,7 +804,9 @@ int cyc_model_create(cyc_model** out, int32_t max_batch, uint32_t flags, void* s
             dal(&m->dz, (int64_t)max_batch * NOUT) == hipSuccess && dal(&m->da, (int64_t)CH * BL) == hipSuccess &&
             dal(&m->partial, (int64_t)nb((int64_t)max_batch * NOUT)) == hipSuccess && dal(&m->tw, LEN / 2) == hipSuccess;
   m->ws_cap = (int64_t)1 << 24;
-  ok = ok && dal(&m->ws, m->ws_cap) == hipSuccess;
+  ok = ok && dal(&m->ws, m->ws_cap) == hipSuccess && dal(&m->pfeat, (int64_t)CIN * BL) == hipSuccess &&
+       dal(&m->pprob, (int64_t)max_batch * NOUT) == hipSuccess &&
+       dal(&m->psel, (int64_t)max_batch * NOUT) == hipSuccess;
   for (int i = 0; i < NCONV && ok; ++i)
     ok = dal(&m->u[i], (int64_t)CH * BL) == hipSuccess && dal(&m->a[i], (int64_t)CH * BL) == hipSuccess;
   if (!ok) {
@@ -860,6 +902,26 @@ int cyc_select(const float* d_prob, int32_t n, int32_t topk, int32_t width, int3
     return CYC_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(select_kernel, dim3(n), dim3(256), 0, st, d_prob, n, topk, width, zero_bin, d_sel, d_conf);
+  return hipGetLastError() == hipSuccess ? CYC_OK : CYC_EDEVICE;
+}
+
+int cyc_propose(cyc_model* m, const void* d_x, int32_t n_windows, int32_t topk, int32_t width, int32_t zero_bin,
+                float theta, int32_t* d_bins, int32_t* d_n_bins, float* d_conf, uint8_t* d_fallback, void* stream) {
+  if (!m || !d_x || !d_bins || !d_n_bins || !d_conf || !d_fallback || n_windows < 1 || n_windows > m->maxb ||
+      topk < 0 || topk > NOUT || width < 0 || width >= NOUT / 2 || zero_bin < -1 || zero_bin >= NOUT ||
+      !(theta == theta))
+    return CYC_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int n = n_windows;
+  hipLaunchKernelGGL(spectra_kernel, dim3(n * 3), dim3(256), 0, st, reinterpret_cast<const float2*>(d_x), m->tw,
+                     m->pfeat, n);
+  if (model_forward(m, m->pfeat, n, st) != hipSuccess) return CYC_EDEVICE;
+  const int64_t nz = (int64_t)n * NOUT;
+  hipLaunchKernelGGL(head_out_kernel, dim3(nb(nz)), dim3(256), 0, st, m->z, m->w + m->offbh, m->pprob,
+                     (const float*)nullptr, (float*)nullptr, 0.f, (double*)nullptr, nz);
+  hipLaunchKernelGGL(select_kernel, dim3(n), dim3(256), 0, st, m->pprob, n, topk, width, zero_bin, m->psel, d_conf);
+  hipLaunchKernelGGL(compact_bins_kernel, dim3(n), dim3(256), 0, st, m->psel, d_conf, theta, d_bins, d_n_bins,
+                     d_fallback);
   return hipGetLastError() == hipSuccess ? CYC_OK : CYC_EDEVICE;
 }
 

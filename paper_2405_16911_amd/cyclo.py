@@ -73,6 +73,9 @@ SIGNATURES = {
                                          ctypes.c_void_p]),
     "cyc_model_gradients": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                            ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "cyc_propose": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cyc_model_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                             ctypes.c_float, ctypes.c_float, ctypes.POINTER(ctypes.c_double),
                                             ctypes.c_void_p]),
@@ -435,6 +438,33 @@ class ProposalModel:
                                           float(weight_decay), ctypes.byref(loss), _stream_handle(stream)),
                "cyc_model_train_step")
         return loss.value
+
+    def propose(self, x, topk: int = 16, width: int = 2, zero_bin: int = N_COARSE // 2, theta: float = 0.0,
+                stream=None):
+        """x: complex64 CUDA tensor of n*65536 samples -> (bins int32 [n, 1024] (-1 padded), n_bins int32 [n],
+        conf float [n], fallback uint8 [n]) on the GPU."""
+        import torch
+        n = x.numel() // WINDOW
+        bins = torch.empty((n, N_COARSE), dtype=torch.int32, device=x.device)
+        nb_ = torch.empty(n, dtype=torch.int32, device=x.device)
+        conf = torch.empty(n, dtype=torch.float32, device=x.device)
+        fb = torch.empty(n, dtype=torch.uint8, device=x.device)
+        _check(lib().cyc_propose(self._m, _p(x), n, int(topk), int(width), int(zero_bin), float(theta), _p(bins),
+                                 _p(nb_), _p(conf), _p(fb), _stream_handle(stream)), "cyc_propose")
+        return bins, nb_, conf, fb
+
+    @staticmethod
+    def save(path: str, params: np.ndarray):
+        """Writes an FP32 parameter vector (as from get_params) to a .npy file."""
+        np.save(path, np.asarray(params, dtype=np.float32), allow_pickle=False)
+
+    @staticmethod
+    def load(path: str) -> np.ndarray:
+        """Reads a parameter vector written by save (for set_params)."""
+        v = np.load(path, allow_pickle=False)
+        if v.dtype != np.float32 or v.ndim != 1 or v.size != ProposalModel.num_params():
+            raise ValueError("not a parameter vector of this network")
+        return v
 
     def close(self):
         if self._m is not None:

@@ -5,6 +5,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_2405_16911_amd import cyclo
@@ -111,3 +112,25 @@ def test_batch_invalid_arguments(L):
     assert L.cyc_batch_reset(None) == cyclo.CYC_EINVAL
     assert L.cyc_batch_query(None, None, None, None) == cyclo.CYC_EINVAL
     L.cyc_batch_destroy(None)
+
+
+def test_proposal_invalid_arguments(L):
+    out = ctypes.c_void_p()
+    assert L.cyc_model_create(None, 4, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_model_create(ctypes.byref(out), 0, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_model_create(ctypes.byref(out), 4, 0x2, None) == cyclo.CYC_EUNSUPPORTED
+    assert out.value is None
+    assert L.cyc_model_num_params() == 67197568
+    assert L.cyc_propose(None, None, 1, 16, 2, 512, 0.0, None, None, None, None, None) == cyclo.CYC_EINVAL
+    assert L.cyc_select(None, 1, 16, 2, 512, None, None, None) == cyclo.CYC_EINVAL
+    assert L.cyc_peak_labels(None, None, 1, 64, 8, 0, 7.0, None, None) == cyclo.CYC_EINVAL
+    L.cyc_model_destroy(None)
+
+
+def test_parameter_file_round_trip(tmp_path):
+    v = np.arange(cyclo.ProposalModel.num_params(), dtype=np.float32) * np.float32(1e-3)
+    cyclo.ProposalModel.save(str(tmp_path / "p.npy"), v)
+    assert np.array_equal(cyclo.ProposalModel.load(str(tmp_path / "p.npy")), v)
+    np.save(tmp_path / "bad.npy", v[:10])
+    with pytest.raises(ValueError):
+        cyclo.ProposalModel.load(str(tmp_path / "bad.npy"))

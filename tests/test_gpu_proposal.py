@@ -178,3 +178,28 @@ def test_label_noise_scale_matches_oracle_median(cy):
                              n_coarse=n_coarse, zero_bin=-1).cpu().numpy()
     assert ref.tolist() == [0, 0, 0, 0, 0, 1, 0, 0]
     assert np.array_equal(lab, ref.astype(np.float32))
+
+
+def test_propose_equals_its_steps_and_the_oracle_selection(cy):
+    # cyc_propose (spectra -> network -> selection -> compaction) against the
+    # separate calls on the same windows, and its bins against the oracle's
+    # selection of the same probabilities
+    n = 3
+    x = torch.from_numpy(np.concatenate([siggen.mixed_stream(5, 100 + i, n=65536)[0] for i in range(n)])).to("cuda")
+    m = cy.ProposalModel(4, cy.CYC_OP_FP32)
+    m.set_params(_flat(_params(7)))
+    bins, nbins, conf, fb = m.propose(x, topk=16, width=2, zero_bin=512, theta=0.5)
+    prob = m.forward(m.spectra(x))
+    sel, conf2 = cy.cyc_select(prob, topk=16, width=2, zero_bin=512)
+    bins, nbins, conf, fb = bins.cpu().numpy(), nbins.cpu().numpy(), conf.cpu().numpy(), fb.cpu().numpy()
+    prob, sel, conf2 = prob.cpu().numpy(), sel.cpu().numpy(), conf2.cpu().numpy()
+    m.close()
+    for i in range(n):
+        want = np.nonzero(sel[i])[0]
+        assert nbins[i] == want.size
+        assert list(bins[i, :nbins[i]]) == list(want)
+        assert (bins[i, nbins[i]:] == -1).all()
+        assert conf[i] == conf2[i] and fb[i] == (1 if conf[i] < 0.5 else 0)
+        s_ref, c_ref = P.select(prob[i].astype(np.float64), k=16, width=2, zero_bin=512)
+        assert list(want) == list(s_ref)
+        assert abs(conf[i] - c_ref) < 1e-6
