@@ -345,10 +345,12 @@ __device__ __forceinline__ void contract_f32_tile(const ContractArgs& a, TileId 
 // K block.  The Hankel operand is kept as eight copies (cr, sh) holding the
 // pairs (re, -im) (cr = 0) or (im, re) (cr = 1) of the window shifted by
 // sh = 0..3 samples, so every 16-byte fragment read is aligned for any lag.
-// Copy (cr, sh) starts at word cr*CO + sh*ZP with ZP = 8 and CO = 4 (mod 32):
-// the eight copies that a group of eight lanes reads at one offset, and the
-// eight 16-byte blocks that eight lanes write while staging, fall on disjoint
-// banks.
+// Copy (cr, sh) starts at word cr*CO + sh*ZP with ZP = 8 (mod 64) and
+// CO = 4 ZP (= 32 mod 64).  A 16-byte fragment read is served sixteen lanes at
+// a time from 64 four-byte banks; the sixteen lanes of a group read copies
+// (cr, sh) at fragment offsets 0 and +4 words, i.e. in 16-byte bank units
+// 8 cr + 2 sh + {0, 1} (mod 16): all sixteen units differ, so the reads are
+// free of bank conflicts.
 template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS, int SCHED>
 __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId tid_in) {
   using O = Op<PREC>;
@@ -360,9 +362,10 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
   constexpr int G = KS * AW / NT;
   static_assert(G >= 4 && G * NT == KS * AW && KS % G == 0 && G % 4 == 0, "B-gen split");
   constexpr int ZW = KS + TW;                    // entries per shifted copy (multiple of 4)
-  constexpr int ZP = ((ZW + 31) / 32) * 32 + 8;  // copy pitch, = 8 (mod 32)
-  constexpr int CO = 4 * ZP + 4;                 // offset of the cr = 1 copies, = 4 (mod 32)
+  constexpr int ZP = ((ZW + 55) / 64) * 64 + 8;  // copy pitch >= ZW, = 8 (mod 64)
+  constexpr int CO = 4 * ZP;                     // offset of the cr = 1 copies, = 32 (mod 64)
   constexpr int ZS = CO + 4 * ZP;                // words per buffer
+  static_assert(ZP >= ZW && ZP % 64 == 8 && CO % 64 == 32, "Hankel copy layout");
   constexpr int XW = ZW + 4;                     // staged Hankel samples (ZW + 3 are read)
   constexpr int BP = KS + 4;                     // B row pitch (uint32), rows 16-byte aligned
   constexpr int NB = SPLIT ? 2 : 1;
@@ -607,8 +610,8 @@ __global__ __launch_bounds__(64, 1) void contract_rg(ContractArgs a) {
   static_assert(KS % 8 == 0, "shape");
   constexpr int NKB = KS / 8;                    // 8-sample K blocks per step
   constexpr int ZW = KS + TW;
-  constexpr int ZP = ((ZW + 31) / 32) * 32 + 8;  // see contract_16
-  constexpr int CO = 4 * ZP + 4;
+  constexpr int ZP = ((ZW + 55) / 64) * 64 + 8;  // see contract_16
+  constexpr int CO = 4 * ZP;
   constexpr int ZS = CO + 4 * ZP;
   constexpr int XW = ZW + 4;
   constexpr int ZU = ZW;

@@ -77,9 +77,12 @@ class FullGrid:
 
     def __init__(self, flags=cyclo.CYC_OP_BF16):
         import torch
+        # the kernel configuration the autotuner finds fastest for this shape
+        cyclo.cyc_autotune(FINE, T_LAG, flags)
         self.st = cyclo.CyclicStream(FINE_GRID, T_LAG, flags)
         self.R = torch.empty((T_LAG, FINE), dtype=torch.complex64, device="cuda")
         self.Rc = torch.empty_like(self.R)
+        self.zero = torch.zeros_like(self.R)
 
     def tables(self, x):
         self.st.reset()
@@ -92,13 +95,18 @@ class FullGrid:
 
 
 def label_windows(xd, fg: FullGrid, thresh: float = 7.0):
-    """Labels [n, 1024] (GPU float) of device windows xd [n, 65536]."""
+    """Labels of device windows xd [n, 65536]: (non-conjugate, conjugate), each [n, 1024] on the GPU.
+
+    The label of a coarse bin is the larger of the two (a table of zeros has no peaks).
+    """
     import torch
-    out = torch.empty((xd.shape[0], N_COARSE), dtype=torch.float32, device="cuda")
+    acf = torch.empty((xd.shape[0], N_COARSE), dtype=torch.float32, device="cuda")
+    conj = torch.empty_like(acf)
     for i in range(xd.shape[0]):
         R, Rc = fg.tables(xd[i])
-        out[i] = cyclo.cyc_peak_labels(R, Rc, N_COARSE, ZERO_BIN, thresh)
-    return out
+        acf[i] = cyclo.cyc_peak_labels(R, fg.zero, N_COARSE, ZERO_BIN, thresh)
+        conj[i] = cyclo.cyc_peak_labels(fg.zero, Rc, N_COARSE, ZERO_BIN, thresh)
+    return acf, conj
 
 
 def heuristic_scores(feat):
@@ -118,14 +126,38 @@ def miss_rate(sel, labels, fell_back):
     return missed / max(total, 1), int(missed), int(total)
 
 
-def train(model, feat, labels, epochs: int, batch: int, lr: float, wd: float, seed: int = 0, log=None,
-          val=None):
-    """AdamW epochs over shuffled batches (cosine learning-rate decay).
+def shifted_batch(feat, acf, conj, idx, shifts):
+    """Features and labels of windows idx as if each had been shifted in frequency.
 
-    With val = (features, labels) the validation loss is taken after every
-    epoch and the parameters of the best epoch are kept.
+    A carrier shift x[n] exp(j2pi k n / 1024) moves the Welch spectrum of x by
+    k bins and that of x^2 by 2k bins (each segment is 1024 samples long, so the
+    shift is a whole number of bins and only the segment phases change), leaves
+    |x|^2 unchanged, moves every conjugate cycle frequency by 2k / 1024 (2k
+    coarse bins) and leaves the non-conjugate ones in place.  shifts: int64 [B]
+    on the GPU.  Returns ([3, B, 1024] features, [B, 1024] labels).
     """
     import torch
+    pos = torch.arange(N_COARSE, device=feat.device)
+    src1 = (pos[None, :] - shifts[:, None]) % N_COARSE
+    src2 = (pos[None, :] - 2 * shifts[:, None]) % N_COARSE
+    f0 = torch.gather(feat[0, idx], 1, src1)
+    f1 = torch.gather(feat[1, idx], 1, src2)
+    f2 = feat[2, idx]
+    lab = torch.maximum(acf[idx], torch.gather(conj[idx], 1, src2))
+    return torch.stack([f0, f1, f2]).contiguous(), lab.contiguous()
+
+
+def train(model, feat, labels, epochs: int, batch: int, lr: float, wd: float, seed: int = 0, log=None,
+          val=None, augment: bool = True):
+    """AdamW epochs over shuffled batches (cosine learning-rate decay).
+
+    labels = (non-conjugate, conjugate) label tensors; with augment every
+    window of a batch is seen at a random carrier shift (shifted_batch).  With
+    val = (features, labels) the validation loss is taken after every epoch
+    and the parameters of the best epoch are kept.
+    """
+    import torch
+    acf, conj = labels
     n = feat.shape[1]
     rng = np.random.default_rng(seed)
     losses, val_losses = [], []
@@ -139,8 +171,8 @@ def train(model, feat, labels, epochs: int, batch: int, lr: float, wd: float, se
         t = time.perf_counter()
         for s in range(0, n - batch + 1, batch):
             idx = torch.from_numpy(order[s:s + batch]).to("cuda")
-            fb = feat[:, idx, :].contiguous()
-            lb = labels[idx].contiguous()
+            k = rng.integers(0, N_COARSE, size=batch) if augment else np.zeros(batch, dtype=np.int64)
+            fb, lb = shifted_batch(feat, acf, conj, idx, torch.from_numpy(k).to("cuda"))
             ep_loss.append(model.train_step(fb, lb, lr_ep, wd))
             steps += 1
         torch.cuda.synchronize()
@@ -193,36 +225,39 @@ def dataset(model, fg: FullGrid, seed: int, first: int, n: int, keep_windows: bo
             log=None, pool=None):
     """Features [3, n, 1024] and labels [n, 1024] (GPU) of n windows, made chunk by chunk."""
     import torch
-    feats, labs, wins = [], [], []
+    feats, acfs, conjs, wins = [], [], [], []
     for s in range(0, n, chunk):
         m = min(chunk, n - s)
         xd = torch.from_numpy(make_windows(seed, first + s, m, pool)).to("cuda")
-        labs.append(label_windows(xd, fg))
+        a, c = label_windows(xd, fg)
+        acfs.append(a)
+        conjs.append(c)
         feats.append(model.spectra(xd.reshape(-1)))
         if keep_windows:
             wins.append(xd)
         if log:
             log(f"  windows {first + s}..{first + s + m - 1} labelled")
     feat = torch.cat(feats, dim=1)
-    lab = torch.cat(labs)
-    return feat, lab, (torch.cat(wins) if keep_windows else None)
+    acf, conj = torch.cat(acfs), torch.cat(conjs)
+    return feat, (acf, conj), (torch.cat(wins) if keep_windows else None)
 
 
-def run(n_train=4096, n_val=512, n_test=512, epochs=20, batch=64, lr=1e-3, wd=0.1, seed=5,
-        target_miss=0.01, log=print, pool=None):
+def run(n_train=4096, n_val=512, n_test=512, epochs=30, batch=128, lr=2e-3, wd=0.1, seed=5,
+        target_miss=0.01, log=print, pool=None, augment=True):
     import torch
     t0 = time.time()
     res = {"config": dict(n_train=n_train, n_val=n_val, n_test=n_test, epochs=epochs, batch=batch, lr=lr,
                           weight_decay=wd, seed=seed, window=WINDOW, fine_bins=FINE, coarse_bins=N_COARSE,
                           lags=T_LAG, select="top16+-2 and the alpha=0 bin", label_threshold=7.0,
-                          target_miss=target_miss)}
+                          target_miss=target_miss, augment=augment)}
     fg = FullGrid()
     model = cyclo.ProposalModel(max(batch, 512), cyclo.CYC_OP_BF16)
     torch.cuda.synchronize()
     t1 = time.time()
-    f_tr, l_tr, _ = dataset(model, fg, seed, 0, n_train, log=log, pool=pool)
-    f_va, l_va, _ = dataset(model, fg, seed, n_train, n_val, log=log, pool=pool)
-    f_te, l_te, x_te = dataset(model, fg, seed, n_train + n_val, n_test, keep_windows=True, log=log, pool=pool)
+    f_tr, ls_tr, _ = dataset(model, fg, seed, 0, n_train, log=log, pool=pool)
+    f_va, ls_va, _ = dataset(model, fg, seed, n_train, n_val, log=log, pool=pool)
+    f_te, ls_te, x_te = dataset(model, fg, seed, n_train + n_val, n_test, keep_windows=True, log=log, pool=pool)
+    l_tr, l_va, l_te = (torch.maximum(*ls) for ls in (ls_tr, ls_va, ls_te))
     torch.cuda.synchronize()
     res["labelling_s"] = time.time() - t1
     res["positives_per_window"] = float(torch.cat([l_tr, l_va, l_te]).sum(1).mean().item())
@@ -232,7 +267,7 @@ def run(n_train=4096, n_val=512, n_test=512, epochs=20, batch=64, lr=1e-3, wd=0.
     p_untrained = probabilities(model, f_te, 512)
     # training
     t2 = time.time()
-    tr = train(model, f_tr, l_tr, epochs, batch, lr, wd, seed, log, val=(f_va, l_va))
+    tr = train(model, f_tr, ls_tr, epochs, batch, lr, wd, seed, log, val=(f_va, l_va), augment=augment)
     torch.cuda.synchronize()
     res["train"] = dict(seconds=time.time() - t2, steps=tr["steps"], ms_per_step=tr["ms_per_step"],
                         loss_first_epoch=tr["losses"][0], loss_last_epoch=tr["losses"][-1],
@@ -360,19 +395,20 @@ if __name__ == "__main__":
     ap.add_argument("--n-train", type=int, default=4096)
     ap.add_argument("--n-val", type=int, default=512)
     ap.add_argument("--n-test", type=int, default=512)
-    ap.add_argument("--epochs", type=int, default=20)
-    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--batch", type=int, default=128)
     ap.add_argument("--out", default="")
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--wd", type=float, default=0.1)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--target-miss", type=float, default=0.01)
+    ap.add_argument("--no-augment", action="store_true")
     a = ap.parse_args()
     import os
     # forked before anything touches the GPU
     with Pool(max(1, min(a.workers, os.cpu_count() or 1))) as pool:
         r = run(a.n_train, a.n_val, a.n_test, a.epochs, batch=a.batch, lr=a.lr, wd=a.wd,
-                target_miss=a.target_miss, pool=pool)
+                target_miss=a.target_miss, pool=pool, augment=not a.no_augment)
     s = json.dumps(r, indent=1)
     print(s)
     if a.out:

@@ -27,8 +27,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_trained_proposal_gains_over_untrained_and_heuristic(tmp_path):
     out = tmp_path / "proposal.json"
     cmd = [sys.executable, "-u", "-m", "paper_2405_16911_amd.proposal", "--n-train", "4096", "--n-val", "512",
-           "--n-test", "256", "--epochs", "20", "--batch", "64", "--wd", "0.1", "--target-miss", "0.05",
-           "--out", str(out)]
+           "--n-test", "256", "--epochs", "20", "--batch", "128", "--lr", "2e-3", "--wd", "0.1",
+           "--target-miss", "0.05", "--out", str(out)]
     print("  " + " ".join(cmd[3:]), flush=True)
     p = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True, timeout=400)
     print(p.stdout[-3000:], p.stderr[-2000:], flush=True)
