@@ -7,9 +7,10 @@ the timed region.  Default workload: QPSK with a root-raised-cosine pulse
 complex64 samples pushed in 256 blocks of 65536, lags 0..127, 4096 cycle
 frequencies alpha_k = -1/2 + k/4096, FP32 operands.
 
-Extra forms in the same line: the 512-stream batch form and the learned
-proposal (trained in the run on 8192 windows, then timed against the full fine
-grid on held-out windows).
+Extra forms in the same line: the 512-stream batch form, the learned proposal
+(trained in the run, then timed against the dense full fine grid on held-out
+windows) and the uniform-grid form (fold + FFT) on the same record, which is
+exact on uniform power-of-two grids and quoted as context only.
 
 Output: one JSON line (metric, value, ..., roofline, cpu_baseline, forms).
 value = (alpha, tau)*samples per second = A * T * N_used / seconds per step.
@@ -230,6 +231,41 @@ def run_batch(bw, prec: str, steps: int, warmup: int, compare_single: bool = Fal
     return out
 
 
+def run_grid(wl, steps: int, warmup: int):
+    """The uniform-grid form (fold + FP64 FFT) on the same record and grid: exact, and
+    available only because the grid is uniform with a power-of-two size; context for
+    the dense contraction, never part of its roofline."""
+    import torch
+    from paper_2405_16911_amd import cyclo
+    T, alphas, blk = wl["T"], wl["alphas"], wl["block"]
+    A = alphas.size
+    alpha0 = float(alphas[0])
+    assert np.allclose(alphas, alpha0 + np.arange(A) / A, rtol=0, atol=1e-15)
+    x = torch.from_numpy(wl["x"]).to("cuda")
+    g = cyclo.GridStream(alpha0, A, T)
+    R = torch.empty((T, A), dtype=torch.complex64, device="cuda")
+    Rc = torch.empty_like(R)
+    blocks = [x[i:i + blk] for i in range(0, x.numel(), blk)]
+
+    def step():
+        g.reset()
+        for b in blocks:
+            g.push(b)
+        return g.read_into(R, Rc)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        n_used = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    g.close()
+    return dict(workload=wl["desc"] + "_uniform_grid_fold_fft", value=float(A) * T * n_used / dt,
+                ms_per_step=1e3 * dt, arithmetic="FP64 fold and FFT", exact_on="uniform grids, A a power of two")
+
+
 def run_proposal(n_train: int, pool):
     """Learned proposal trained in this run, then timed against the full fine grid.
 
@@ -254,6 +290,7 @@ def run_proposal(n_train: int, pool):
                 max_rel_diff_vs_full_grid=sp["max_rel_diff_vs_full_grid"],
                 evaluated_alphas_per_window=sp["evaluated_alphas_per_window"],
                 full_grid_ms_per_window=1e3 * sp["full_grid_s"] / sp["windows"],
+                full_grid_fft_ms_per_window=1e3 * sp["full_grid_fft_s"] / sp["windows"],
                 proposal_ms_per_window=1e3 * sp["proposal_path_s"] / sp["windows"],
                 theta_curve=r["theta_curve"], train=r["train"], labelling_s=r["labelling_s"],
                 positives_per_window=r["positives_per_window"],
@@ -284,9 +321,10 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=6 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--forms", default="batch,proposal",
-                    help="extra forms measured after the main workload: any of 'batch', 'proposal' ('' for none)")
-    ap.add_argument("--proposal-train", type=int, default=8192,
+    ap.add_argument("--forms", default="batch,proposal,grid",
+                    help="extra forms measured after the main workload: any of 'batch', 'proposal', 'grid' "
+                         "('' for none)")
+    ap.add_argument("--proposal-train", type=int, default=16384,
                     help="training windows of the learned proposal trained inside the run")
     ap.add_argument("--batch-streams", type=int, default=512)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -357,6 +395,9 @@ def main():
                               runs=[run_batch(bw, "bf16", 3, 1, compare_single=True),
                                     run_batch(bw, "f32", 2, 1)])
         del bw
+    if "grid" in forms_wanted and args.workload == "qpsk_rrc_2p24":
+        forms["grid"] = run_grid(wl, max(3, args.steps), 1)
+        forms["grid"]["speedup_vs_dense_main"] = forms["grid"]["value"] / value
     if "proposal" in forms_wanted:
         forms["proposal"] = run_proposal(args.proposal_train, pool)
         pool.close()

@@ -213,6 +213,32 @@ void cyc_batch_destroy(cyc_batch* b);
 int cyc_batch_query(const cyc_batch* b, int32_t* kernel_cfg, int32_t* rounds, int32_t* graph);
 
 /*
+ * Uniform-grid form: the same tables R, Rc (definition and conventions as
+ * cyc_create .. cyc_read) on the whole grid alpha_k = alpha0 + k / n_alpha,
+ * k = 0 .. n_alpha-1, evaluated by folding and an FFT (the paper's Full mode,
+ * Sec. 4, covers a grid of cycle frequencies with an FFT).  Because
+ * exp(-j2pi k n / A) depends only on n mod A, a push adds every product
+ * x[n+t] conj(x[n]) exp(-j2pi frac(alpha0 n)) (and the conjugate one) into the
+ * fold bin n mod A, and a read takes one A-point DFT per (table, lag).
+ *   n_alpha : A, a power of two, 2 <= A <= 65536 (else CYC_EUNSUPPORTED).
+ *   n_lag   : T, 1 <= T <= 4096.   alpha0 : any finite real.
+ *   flags   : 0 or CYC_OUT_C128 (table element type; the arithmetic is FP64).
+ * push / read / reset / destroy behave as cyc_push / cyc_read / cyc_reset /
+ * cyc_destroy: asynchronous on `stream`, any segmentation gives the same bits,
+ * read leaves the state unchanged, N_used = max(0, L - T + 1) (zero tables and
+ * CYC_OK when it is 0).  Work per product is O(T); per read O(T A log A).
+ * State memory: 32 T A bytes (64 T A when A > 8192) plus a 16 MiB phase
+ * buffer.  Errors as the single-stream calls.
+ */
+typedef struct cyc_grid cyc_grid;
+int cyc_grid_create(cyc_grid** out, double alpha0, int32_t n_alpha, int32_t n_lag, uint32_t flags,
+                    void* stream);
+int cyc_grid_push(cyc_grid* g, const void* d_x, int64_t n, void* stream);
+int cyc_grid_read(cyc_grid* g, void* d_R, void* d_Rc, int64_t* n_used, void* stream);
+int cyc_grid_reset(cyc_grid* g);
+void cyc_grid_destroy(cyc_grid* g);
+
+/*
  * Learned cycle-frequency proposal (coarse stage of a coarse-to-fine
  * estimator; the paper's related work in Sec. 1 describes the two-stage idea
  * and Sec. 6 names cycle-frequency estimation as future work).

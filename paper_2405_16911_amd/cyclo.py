@@ -73,6 +73,13 @@ SIGNATURES = {
                                          ctypes.c_void_p]),
     "cyc_model_gradients": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                            ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "cyc_grid_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_uint32, ctypes.c_void_p]),
+    "cyc_grid_push": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "cyc_grid_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+    "cyc_grid_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "cyc_grid_destroy": (None, [ctypes.c_void_p]),
     "cyc_propose": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -355,6 +362,59 @@ class CyclicBatch:
         if self._b is not None:
             cyc_batch_destroy(self._b)
             self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------- uniform grids
+
+class GridStream:
+    """Tables on the whole grid alpha_k = alpha0 + k / n_alpha by fold and FFT (n_alpha a power of two)."""
+
+    def __init__(self, alpha0: float, n_alpha: int, n_lag: int, flags: int = 0, stream=None):
+        self.alpha0, self.A, self.T, self.flags = float(alpha0), int(n_alpha), int(n_lag), int(flags)
+        out = ctypes.c_void_p()
+        _check(lib().cyc_grid_create(ctypes.byref(out), self.alpha0, self.A, self.T, self.flags,
+                                     _stream_handle(stream)), "cyc_grid_create")
+        self._g = out
+
+    @property
+    def alphas(self) -> np.ndarray:
+        return self.alpha0 + np.arange(self.A) / self.A
+
+    def push(self, x, stream=None):
+        import torch
+        if x.dtype != torch.complex64 or not x.is_cuda or not x.is_contiguous():
+            raise ValueError("x must be a contiguous complex64 CUDA tensor")
+        _check(lib().cyc_grid_push(self._g, ctypes.c_void_p(x.data_ptr()), int(x.numel()), _stream_handle(stream)),
+               "cyc_grid_push")
+
+    def read_into(self, R=None, Rc=None, stream=None) -> int:
+        nu = ctypes.c_int64()
+        _check(lib().cyc_grid_read(self._g, _p(R), _p(Rc), ctypes.byref(nu), _stream_handle(stream)),
+               "cyc_grid_read")
+        return nu.value
+
+    def read(self, stream=None):
+        """Returns (R, Rc, n_used) as new [T, A] tensors on the GPU."""
+        import torch
+        dt = torch.complex128 if self.flags & CYC_OUT_C128 else torch.complex64
+        R = torch.empty((self.T, self.A), dtype=dt, device="cuda")
+        Rc = torch.empty_like(R)
+        n = self.read_into(R, Rc, stream)
+        return R, Rc, n
+
+    def reset(self):
+        _check(lib().cyc_grid_reset(self._g), "cyc_grid_reset")
+
+    def close(self):
+        if self._g is not None:
+            lib().cyc_grid_destroy(self._g)
+            self._g = None
 
     def __del__(self):
         try:

@@ -4,8 +4,9 @@ Orchestration over the C ABI only (every numeric step runs in the HIP
 library):
 
 * windows: 65536-sample records of the mixed-modulation workload;
-* labels: the full-grid estimator (fine grid alpha_j = -1/2 + j/65536, lags
-  0..63) on each window, reduced by ``cyc_peak_labels`` to 1024 coarse bins;
+* labels: the full-grid tables (fine grid alpha_j = -1/2 + j/65536, lags
+  0..63; the uniform-grid form, FP64) of each window, reduced by
+  ``cyc_peak_labels`` to 1024 coarse bins;
 * features: ``cyc_model_spectra``; training: ``cyc_model_train_step``;
 * proposal: network probabilities -> ``cyc_select`` (top-16 coarse bins +-2,
   the alpha = 0 bin always) -> the exact estimator on the 64 fine bins of each
@@ -73,13 +74,24 @@ def init_params(seed: int, prior_logit: float = -6.0) -> np.ndarray:
 
 
 class FullGrid:
-    """The dense full-fine-grid estimator for one window at a time."""
+    """The full fine grid (65536 alphas, lags 0..63) of one window at a time.
 
-    def __init__(self, flags=cyclo.CYC_OP_BF16):
+    mode "dense": the dense contraction on the alpha list (BF16 operands,
+    autotuned kernel configuration), the baseline the proposal is timed
+    against.  mode "fft": the uniform-grid form (fold + FP64 FFT), used for the
+    labels.
+    """
+
+    def __init__(self, mode: str = "dense", flags=cyclo.CYC_OP_BF16):
         import torch
-        # the kernel configuration the autotuner finds fastest for this shape
-        cyclo.cyc_autotune(FINE, T_LAG, flags)
-        self.st = cyclo.CyclicStream(FINE_GRID, T_LAG, flags)
+        self.mode = mode
+        if mode == "dense":
+            cyclo.cyc_autotune(FINE, T_LAG, flags)
+            self.st = cyclo.CyclicStream(FINE_GRID, T_LAG, flags)
+        elif mode == "fft":
+            self.st = cyclo.GridStream(-0.5, FINE, T_LAG)
+        else:
+            raise ValueError(mode)
         self.R = torch.empty((T_LAG, FINE), dtype=torch.complex64, device="cuda")
         self.Rc = torch.empty_like(self.R)
         self.zero = torch.zeros_like(self.R)
@@ -87,7 +99,10 @@ class FullGrid:
     def tables(self, x):
         self.st.reset()
         self.st.push(x)
-        cyclo.cyc_read(self.st._s, self.R, self.Rc)
+        if self.mode == "dense":
+            cyclo.cyc_read(self.st._s, self.R, self.Rc)
+        else:
+            self.st.read_into(self.R, self.Rc)
         return self.R, self.Rc
 
     def close(self):
@@ -250,7 +265,7 @@ def run(n_train=4096, n_val=512, n_test=512, epochs=30, batch=128, lr=2e-3, wd=0
                           weight_decay=wd, seed=seed, window=WINDOW, fine_bins=FINE, coarse_bins=N_COARSE,
                           lags=T_LAG, select="top16+-2 and the alpha=0 bin", label_threshold=7.0,
                           target_miss=target_miss, augment=augment)}
-    fg = FullGrid()
+    fg = FullGrid("fft")
     model = cyclo.ProposalModel(max(batch, 512), cyclo.CYC_OP_BF16)
     torch.cuda.synchronize()
     t1 = time.time()
@@ -293,7 +308,9 @@ def run(n_train=4096, n_val=512, n_test=512, epochs=30, batch=128, lr=2e-3, wd=0
     sel, conf = cyclo.cyc_select(prob.contiguous(), 16, 2, ZERO_BIN)
     thetas = [0.0, 0.5, 0.8, 0.9, 0.95, 0.98, 0.99, 0.995, 0.999, 1.0]
     curve = theta_curve(conf[:512], sel[:512], l_te[:512], thetas)
-    res["speed"] = speed(model, x_te[:512], fg, theta, conf_curve=[c[2] for c in curve])
+    fd = FullGrid("dense")
+    res["speed"] = speed(model, x_te[:512], fd, theta, conf_curve=[c[2] for c in curve], fft=fg)
+    fd.close()
     res["theta_curve"] = [dict(theta=c[0], miss_rate=c[1], fallback_rate=c[2], predicted_speedup=p)
                           for c, p in zip(curve, res["speed"].pop("predicted_speedup"))]
     log(f"speed: {res['speed']}")
@@ -319,7 +336,7 @@ def _contract_selected(xt, sel_h, idx):
     return out
 
 
-def speed(model, xt, fg: FullGrid, theta: float, conf_curve=None):
+def speed(model, xt, fg: FullGrid, theta: float, conf_curve=None, fft: FullGrid = None):
     """Dense full grid vs. spectra + network + selection + proposal contraction (+ fallbacks).
 
     Measured: the full grid over every window; the front end; the proposal
@@ -335,6 +352,13 @@ def speed(model, xt, fg: FullGrid, theta: float, conf_curve=None):
         fg.tables(xt[i])
     torch.cuda.synchronize()
     t_full = time.perf_counter() - t
+    t_fft = None
+    if fft is not None:
+        t = time.perf_counter()
+        for i in range(n):
+            fft.tables(xt[i])
+        torch.cuda.synchronize()
+        t_fft = time.perf_counter() - t
     t = time.perf_counter()
     feat = model.spectra(xt.reshape(-1))
     prob = model.forward(feat)
@@ -369,7 +393,8 @@ def speed(model, xt, fg: FullGrid, theta: float, conf_curve=None):
             scale = R[0].abs().max().item()
             diff = max(diff, (Rs[j] - R[:, cols]).abs().max().item() / scale,
                        (Rcs[j] - Rc[:, cols]).abs().max().item() / scale)
-    res = dict(windows=n, full_grid_s=t_full, front_end_s=t_front, proposal_contract_no_fallback_s=t_sel,
+    res = dict(windows=n, full_grid_s=t_full, full_grid_fft_s=t_fft, front_end_s=t_front,
+               proposal_contract_no_fallback_s=t_sel,
                proposal_path_s=t_front + t_path, fallback_windows=int(fb.sum()),
                speedup=t_full / (t_front + t_path), speedup_no_fallback=t_full / (t_front + t_sel),
                evaluated_alphas_per_window=float(sel_h.sum(1).mean() * PER),

@@ -134,3 +134,19 @@ def test_parameter_file_round_trip(tmp_path):
     np.save(tmp_path / "bad.npy", v[:10])
     with pytest.raises(ValueError):
         cyclo.ProposalModel.load(str(tmp_path / "bad.npy"))
+
+
+def test_grid_invalid_arguments(L):
+    out = ctypes.c_void_p()
+    assert L.cyc_grid_create(None, 0.0, 64, 4, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_grid_create(ctypes.byref(out), float("nan"), 64, 4, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_grid_create(ctypes.byref(out), 0.0, 64, 0, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_grid_create(ctypes.byref(out), 0.0, 64, 4, cyclo.CYC_OP_BF16, None) == cyclo.CYC_EINVAL
+    assert L.cyc_grid_create(ctypes.byref(out), 0.0, 100, 4, 0, None) == cyclo.CYC_EUNSUPPORTED
+    assert L.cyc_grid_create(ctypes.byref(out), 0.0, 1 << 17, 4, 0, None) == cyclo.CYC_EUNSUPPORTED
+    assert L.cyc_grid_create(ctypes.byref(out), 0.0, 1, 4, 0, None) == cyclo.CYC_EUNSUPPORTED
+    assert out.value is None
+    assert L.cyc_grid_push(None, None, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_grid_read(None, None, None, None, None) == cyclo.CYC_EINVAL
+    assert L.cyc_grid_reset(None) == cyclo.CYC_EINVAL
+    L.cyc_grid_destroy(None)
