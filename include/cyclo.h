@@ -100,6 +100,25 @@ int cyc_push(cyc_state* s, const void* d_x, int64_t n, void* stream);
 int cyc_read(cyc_state* s, void* d_R, void* d_Rc, int64_t* n_used, void* stream);
 
 /*
+ * Two inputs and a lag range of either sign (the block of Sec. 4, Eq. (11):
+ * x[n+m] y*[n] with lags -M .. M in its Set mode).  Lags are
+ * m = lag_min .. lag_min + n_lag - 1; lag m pairs x[k + m] with y[k], and the
+ * phase is referenced to y's index k:
+ *   R [t][a] = (1/N) sum_{n<N} x[n + dx + t] conj(y[n + dy]) exp(-j2pi frac(alpha_a (n + dy)))
+ *   Rc[t][a] = (1/N) sum_{n<N} x[n + dx + t]      y[n + dy]  exp(-j2pi frac(alpha_a (n + dy)))
+ * with dx = max(0, lag_min), dy = max(0, -lag_min), N = max(0, L - (n_lag - 1) - |lag_min|)
+ * over L samples of each input (one count for all lags).  |lag_min| <= 2^20;
+ * the other arguments as cyc_create.  cyc_push2 pushes n samples of each input
+ * (separate device buffers, complex64); cyc_push on such a state uses x for
+ * both inputs; read / reset / destroy / query are the single-input calls.
+ * cyc_push2 on a state made by cyc_create returns CYC_EINVAL.  Results do not
+ * depend on how the samples are split into pushes.
+ */
+int cyc_create2(cyc_state** out, const double* alphas_host, int32_t n_alpha, int64_t lag_min,
+                int32_t n_lag, uint32_t flags, void* stream);
+int cyc_push2(cyc_state* s, const void* d_x, const void* d_y, int64_t n, void* stream);
+
+/*
  * Forget every pushed sample and clear the poison flag; alphas, T and flags
  * are kept.  Afterwards the state behaves exactly like a fresh one.  Host-only
  * (enqueues no device work).  Errors: CYC_EINVAL (s NULL).

@@ -180,6 +180,33 @@ def cyclic_tables(x, alphas=None, T: int = 1, rational=None, chunk: int = 4096):
     return st.read()
 
 
+def cross_tables(x, y, alphas, lag_min: int, T: int):
+    """Two-input form of Sec. 4, Eq. (11), lags m = lag_min .. lag_min + T - 1.
+
+    Lag m pairs x[k + m] with y[k]; the phase is referenced to y's index k:
+      R [t, a] = (1/N) sum_{n<N} x[n + dx + t] conj(y[n + dy]) E(a, n + dy),
+      Rc[t, a] = (1/N) sum_{n<N} x[n + dx + t]      y[n + dy]  E(a, n + dy),
+    dx = max(0, lag_min), dy = max(0, -lag_min), so every product of every lag
+    has both samples; N = max(0, L - (T - 1) - |lag_min|), L = min(len x, len y)
+    (one count for all lags).  With y = x and lag_min = 0 this is cyclic_tables.
+    Returns (R, Rc, N).
+    """
+    x = np.asarray(x).astype(np.complex128).reshape(-1)
+    y = np.asarray(y).astype(np.complex128).reshape(-1)
+    al = _Alphas(alphas, None)
+    L = min(x.size, y.size)
+    dx, dy = max(0, lag_min), max(0, -lag_min)
+    N = max(0, L - (T - 1) - abs(lag_min))
+    A = len(al)
+    if N == 0:
+        z = np.zeros((T, A), dtype=np.complex128)
+        return z, z.copy(), 0
+    yb = y[dy:dy + N]
+    X = np.stack([x[dx + t: dx + t + N] for t in range(T)])
+    E = al.E(np.arange(dy, dy + N, dtype=np.int64))
+    return (X * np.conj(yb)[None, :]) @ E / N, (X * yb[None, :]) @ E / N, N
+
+
 def cyclic_cell(x, alpha: float, tau: int, T: int, n_block: int = 1 << 20):
     """O1: one (alpha, tau) cell of (R, Rc) by a direct dot product over n.
 

@@ -22,7 +22,8 @@ struct VSrc {
 // the chunk-relative twiddle W[l][a] = H[a][l / KS] * Lo[a][l % KS]
 //                                  = exp(-j 2 pi frac(alpha_a l)).
 struct ContractArgs {
-  VSrc v;
+  VSrc v;   // Hankel (leading) samples: product i, lag t reads v[i + t]
+  VSrc vy;  // modulated (trailing) samples: product i reads vy[i]; == v for one input
   int64_t v_off;
   int64_t n_prod;
   int T, A, Kc;

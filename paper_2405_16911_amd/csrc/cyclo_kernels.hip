@@ -166,12 +166,15 @@ struct Stager {
   float2 r[R];
   bool ok[R];
   float2 hv;
-  __device__ __forceinline__ void load(const VSrc& v, int64_t s0, int tau0, int64_t yend,
+  // vx: the leading samples (Hankel window), vy: the trailing samples (the
+  // modulated operand); the same array for one input.
+  __device__ __forceinline__ void load(const VSrc& vx, const VSrc& vy, int64_t s0, int tau0, int64_t yend,
                                        const float2* hp, int tid) {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int idx = tid + i * NT;
       const bool hank = idx < XW;
+      const VSrc& v = hank ? vx : vy;
       const int64_t g = hank ? s0 + tau0 + idx : s0 + (idx - XW);
       const bool valid = idx < N && g < v.n_avail && (hank || g < yend);
       const float2* p = valid ? (g < v.n_pend ? v.pend + g : v.xin + (g - v.n_pend)) : v.pend;
@@ -311,10 +314,10 @@ __device__ __forceinline__ void contract_f32_tile(const ContractArgs& a, TileId 
 
   if (ns > 0) {
     Stager<NT, XW, KS> stg;
-    stg.load(a.v, tl.cbase, tl.tau0, tl.yend, hptr(0), tid);
+    stg.load(a.v, a.vy, tl.cbase, tl.tau0, tl.yend, hptr(0), tid);
     stg.store(&Xh[0][0], &Xy[0][0], tid);
     const float2 h0 = stg.hv;
-    stg.load(a.v, tl.cbase + KS, tl.tau0, tl.yend, hptr(1), tid);
+    stg.load(a.v, a.vy, tl.cbase + KS, tl.tau0, tl.yend, hptr(1), tid);
     stg.store(&Xh[1][0], &Xy[1][0], tid);
     float2 hnext = stg.hv;
     __syncthreads();
@@ -324,7 +327,7 @@ __device__ __forceinline__ void contract_f32_tile(const ContractArgs& a, TileId 
     for (int ks = 0; ks + 1 < ns; ++ks) {
       const int buf = ks & 1;
       const int xb2 = xb == 0 ? 2 : xb - 1;  // (ks + 2) % 3
-      stg.load(a.v, tl.cbase + (int64_t)(ks + 2) * KS, tl.tau0, tl.yend, hptr(ks + 2), tid);
+      stg.load(a.v, a.vy, tl.cbase + (int64_t)(ks + 2) * KS, tl.tau0, tl.yend, hptr(ks + 2), tid);
       mfma_step(xb, buf);
       produce(buf ^ 1, hnext);
       stg.store(&Xh[xb2][0], &Xy[buf][0], tid);
@@ -485,10 +488,10 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
 
   if (ns > 0) {
     Stager<NT, XW, KS> stg;
-    stg.load(a.v, tl.cbase, tl.tau0, tl.yend, hptr(0), tid);
+    stg.load(a.v, a.vy, tl.cbase, tl.tau0, tl.yend, hptr(0), tid);
     stg.store(&Xh[0][0], &Xy[0][0], tid);
     const float2 h0 = stg.hv;
-    stg.load(a.v, tl.cbase + KS, tl.tau0, tl.yend, hptr(1), tid);
+    stg.load(a.v, a.vy, tl.cbase + KS, tl.tau0, tl.yend, hptr(1), tid);
     stg.store(&Xh[1][0], &Xy[1][0], tid);
     float2 hnext = stg.hv;
     __syncthreads();
@@ -496,7 +499,7 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
     __syncthreads();
     for (int ks = 0; ks + 1 < ns; ++ks) {
       const int buf = ks & 1;
-      stg.load(a.v, tl.cbase + (int64_t)(ks + 2) * KS, tl.tau0, tl.yend, hptr(ks + 2), tid);
+      stg.load(a.v, a.vy, tl.cbase + (int64_t)(ks + 2) * KS, tl.tau0, tl.yend, hptr(ks + 2), tid);
       mfma_step(buf);
       produce(buf ^ 1, hnext);
       stg.store(&Xh[buf][0], &Xy[buf][0], tid);
@@ -548,6 +551,7 @@ __device__ __forceinline__ int next_item(int* counter) {
 __device__ __forceinline__ ContractArgs job_args(const BatchArgs& b, const BJob& j) {
   ContractArgs a;
   a.v = j.v;
+  a.vy = j.v;
   a.v_off = j.v_off;
   a.n_prod = j.n_prod;
   a.T = b.T;
@@ -745,11 +749,11 @@ __global__ __launch_bounds__(64, 1) void contract_rg(ContractArgs a) {
   if (ns > 0) {
     Stager<NT, XW, KS> stg;
     float2 hc[NA], hn[NA], hnn[NA];
-    stg.load(a.v, tl.cbase, tl.tau0, tl.yend, Hrow[0] + hidx(0), tid);
+    stg.load(a.v, a.vy, tl.cbase, tl.tau0, tl.yend, Hrow[0] + hidx(0), tid);
     stg.store(&Xh[0][0], &Xy[0][0], tid);
-    stg.load(a.v, tl.cbase + KS, tl.tau0, tl.yend, Hrow[0] + hidx(1), tid);
+    stg.load(a.v, a.vy, tl.cbase + KS, tl.tau0, tl.yend, Hrow[0] + hidx(1), tid);
     stg.store(&Xh[1][0], &Xy[1][0], tid);
-    stg.load(a.v, tl.cbase + 2 * KS, tl.tau0, tl.yend, Hrow[0] + hidx(2), tid);
+    stg.load(a.v, a.vy, tl.cbase + 2 * KS, tl.tau0, tl.yend, Hrow[0] + hidx(2), tid);
 #pragma unroll
     for (int nb = 0; nb < NA; ++nb) {
       hc[nb] = Hrow[nb][hidx(0)];
@@ -769,7 +773,7 @@ __global__ __launch_bounds__(64, 1) void contract_rg(ContractArgs a) {
       float2 h3[NA];
 #pragma unroll
       for (int nb = 0; nb < NA; ++nb) h3[nb] = Hrow[nb][hidx(ks + 3)];
-      stg.load(a.v, tl.cbase + (int64_t)(ks + 3) * KS, tl.tau0, tl.yend, Hrow[0] + hidx(ks + 3), tid);
+      stg.load(a.v, a.vy, tl.cbase + (int64_t)(ks + 3) * KS, tl.tau0, tl.yend, Hrow[0] + hidx(ks + 3), tid);
       build_hankel(w1, zb ^ 1);  // Hankel copies of step ks+1
       load_x(w1, xn);            // samples of step ks+1
 #pragma unroll

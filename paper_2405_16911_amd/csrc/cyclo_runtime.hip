@@ -40,8 +40,12 @@ struct cyc_state {
   float2* Lo = nullptr;
   float2* H = nullptr;
   double2* S = nullptr;
-  float2* pend[2] = {nullptr, nullptr};
+  float2* pend[2] = {nullptr, nullptr};   // leading input x, from absolute index nc + dx
+  float2* pendy[2] = {nullptr, nullptr};  // trailing input y, from nc + dy (two-input states)
   int cur = 0;
+  bool two = false;              // two inputs (cyc_create2)
+  int64_t lag_min = 0, dx = 0, dy = 0, lagabs = 0;
+  int64_t PC = 0;                // pending capacity (samples)
   float2* part = nullptr;
   double2* E = nullptr;
   int64_t L = 0;
@@ -57,6 +61,7 @@ struct cyc_state {
 namespace {
 
 constexpr int kMaxLag = 4096;
+constexpr int64_t kMaxLagShift = 1 << 20;  // |lag_min| of two-input states
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
@@ -169,6 +174,8 @@ void free_state(cyc_state* s) {
   (void)hipFree(s->S);
   (void)hipFree(s->pend[0]);
   (void)hipFree(s->pend[1]);
+  (void)hipFree(s->pendy[0]);
+  (void)hipFree(s->pendy[1]);
   (void)hipFree(s->part);
   (void)hipFree(s->E);
   delete s;
@@ -186,12 +193,13 @@ int fail_device(cyc_state* s) {
 
 }  // namespace
 
-static hipError_t run_contract(cyc_state* s, const VSrc& v, int64_t v_off, int64_t n_prod, int nch,
-                               hipStream_t st) {
+static hipError_t run_contract(cyc_state* s, const VSrc& v, const VSrc& vy, int64_t v_off, int64_t n_prod,
+                               int nch, hipStream_t st) {
   int ncfg = 0;
   const KernelCfg& cfg = kernel_cfgs(&ncfg)[s->cfg];
   ContractArgs a;
   a.v = v;
+  a.vy = vy;
   a.v_off = v_off;
   a.n_prod = n_prod;
   a.T = s->T;
@@ -238,9 +246,10 @@ const char* cyc_status_str(int code) {
   }
 }
 
-int cyc_create(cyc_state** out, const double* alphas_host, int32_t n_alpha, int32_t n_lag,
-               uint32_t flags, void* stream) {
+static int create_state(cyc_state** out, const double* alphas_host, int32_t n_alpha, int64_t lag_min,
+                        int32_t n_lag, uint32_t flags, bool two, void* stream) {
   if (!out || !alphas_host || n_alpha < 1 || n_lag < 1 || n_lag > kMaxLag) return CYC_EINVAL;
+  if (lag_min < -kMaxLagShift || lag_min > kMaxLagShift) return CYC_EINVAL;
   if (flags & ~(CYC_OP_MASK | CYC_TW_SPLIT | CYC_OUT_C128)) return CYC_EINVAL;
   const int prec = (int)(flags & CYC_OP_MASK);
   if (prec == 3) return CYC_EINVAL;
@@ -254,6 +263,11 @@ int cyc_create(cyc_state** out, const double* alphas_host, int32_t n_alpha, int3
   s->T = n_lag;
   s->A = n_alpha;
   s->flags = flags;
+  s->two = two;
+  s->lag_min = lag_min;
+  s->dx = std::max<int64_t>(0, lag_min);
+  s->dy = std::max<int64_t>(0, -lag_min);
+  s->lagabs = lag_min < 0 ? -lag_min : lag_min;
   s->cfg = pick_cfg(prec, split, n_lag, n_alpha);
   if (s->cfg < 0) {
     delete s;
@@ -271,6 +285,8 @@ int cyc_create(cyc_state** out, const double* alphas_host, int32_t n_alpha, int3
   kc = (kc / cfg.ks) * cfg.ks;
   s->Kc = (int)kc;
   s->nsteps = s->Kc / s->KS;
+  // pending samples of either input: < Kc products plus T - 1 + |lag_min| samples
+  s->PC = (int64_t)s->Kc + s->T + s->lagabs;
 
   const int64_t TA2 = 2 * (int64_t)s->T * s->A;
   const int64_t ws_bytes = env_i64("CYC_WORKSPACE_MB", 256) << 20;
@@ -289,8 +305,9 @@ int cyc_create(cyc_state** out, const double* alphas_host, int32_t n_alpha, int3
   int rc = CYC_OK;
   if (dalloc(&s->alpha_r, s->A) != hipSuccess || dalloc(&s->Lo, (size_t)s->A * s->KS) != hipSuccess ||
       dalloc(&s->H, (size_t)s->A * s->nsteps) != hipSuccess || dalloc(&s->S, (size_t)TA2) != hipSuccess ||
-      dalloc(&s->pend[0], (size_t)s->Kc + s->T) != hipSuccess ||
-      dalloc(&s->pend[1], (size_t)s->Kc + s->T) != hipSuccess ||
+      dalloc(&s->pend[0], (size_t)s->PC) != hipSuccess || dalloc(&s->pend[1], (size_t)s->PC) != hipSuccess ||
+      (two && (dalloc(&s->pendy[0], (size_t)s->PC) != hipSuccess ||
+               dalloc(&s->pendy[1], (size_t)s->PC) != hipSuccess)) ||
       dalloc(&s->part, (size_t)s->maxc * TA2) != hipSuccess ||
       dalloc(&s->E, (size_t)s->maxc * s->A) != hipSuccess) {
     rc = CYC_ENOMEM;
@@ -311,52 +328,103 @@ int cyc_create(cyc_state** out, const double* alphas_host, int32_t n_alpha, int3
   return CYC_OK;
 }
 
-int cyc_push(cyc_state* s, const void* d_x, int64_t n, void* stream) {
-  if (!s || n < 0 || (n > 0 && !d_x)) return CYC_EINVAL;
-  if (s->poisoned) return CYC_ESTATE;
-  if (n == 0) return CYC_OK;
-  hipStream_t st = as_stream(stream);
-  const float2* x = reinterpret_cast<const float2*>(d_x);
+int cyc_create(cyc_state** out, const double* alphas_host, int32_t n_alpha, int32_t n_lag,
+               uint32_t flags, void* stream) {
+  return create_state(out, alphas_host, n_alpha, 0, n_lag, flags, false, stream);
+}
 
-  const int64_t n_pend = s->L - s->nc;
-  const int64_t L_new = s->L + n;
-  const int64_t n_used_new = std::max<int64_t>(0, L_new - s->T + 1);
-  const int64_t chunks_new = n_used_new / s->Kc - s->nc / s->Kc;
+int cyc_create2(cyc_state** out, const double* alphas_host, int32_t n_alpha, int64_t lag_min, int32_t n_lag,
+                uint32_t flags, void* stream) {
+  return create_state(out, alphas_host, n_alpha, lag_min, n_lag, flags, true, stream);
+}
 
+}  // extern "C"
+
+namespace {
+
+// The virtual sample array of one input for a push: its pending samples (from
+// absolute index nc + d) followed by the part of the new block from that index
+// on.  n_pend / skip: pending count and leading samples of the block not needed.
+VSrc input_src(const cyc_state* s, float2* const* bufs, int64_t d, const float2* blk, int64_t n, int64_t* n_pend,
+               int64_t* skip) {
+  *n_pend = std::max<int64_t>(0, s->L - (s->nc + d));
+  *skip = std::min<int64_t>(n, std::max<int64_t>(0, s->nc + d - s->L));
   VSrc v;
-  v.pend = s->pend[s->cur];
-  v.xin = x;
-  v.n_pend = n_pend;
-  v.n_avail = n_pend + n;
+  v.pend = bufs[s->cur];
+  v.xin = blk + *skip;
+  v.n_pend = *n_pend;
+  v.n_avail = *n_pend + (n - *skip);
+  return v;
+}
+
+// Keeps one input's samples from absolute index nc_new + d on for the next push.
+hipError_t keep_input(const cyc_state* s, float2* const* bufs, const VSrc& v, int64_t n_pend, int64_t skip,
+                      int64_t d, int64_t n, int64_t shift, int64_t L_new, hipStream_t st) {
+  if (shift == 0) {
+    // no chunk committed: append the new samples behind the pending ones
+    const int64_t add = n - skip;
+    if (add <= 0) return hipSuccess;
+    VSrc a;
+    a.pend = v.xin;
+    a.xin = nullptr;
+    a.n_pend = add;
+    a.n_avail = add;
+    return launch_vcopy(a, 0, add, bufs[s->cur] + n_pend, st);
+  }
+  const int64_t cnt = std::max<int64_t>(0, L_new - (s->nc + shift + d));
+  return cnt > 0 ? launch_vcopy(v, shift, cnt, bufs[s->cur ^ 1], st) : hipSuccess;
+}
+
+// Push of n samples of the leading input x and the trailing input y (y == x
+// for one-input states).  Products n (absolute) pair x[n + dx + t] with
+// y[n + dy] and are committed in chunks aligned to [c Kc, (c + 1) Kc); the
+// chunk phase is referenced to y's index n + dy.
+int push_xy(cyc_state* s, const float2* x, const float2* y, int64_t n, hipStream_t st) {
+  const int64_t L_new = s->L + n;
+  const int64_t n_used_new = std::max<int64_t>(0, L_new - (s->T - 1) - s->lagabs);
+  const int64_t chunks_new = n_used_new / s->Kc - s->nc / s->Kc;
+  int64_t px = 0, sx = 0, py = 0, sy = 0;
+  const VSrc vx = input_src(s, s->pend, s->dx, x, n, &px, &sx);
+  const VSrc vy = s->two ? input_src(s, s->pendy, s->dy, y, n, &py, &sy) : vx;
 
   for (int64_t done = 0; done < chunks_new;) {
     const int nch = (int)std::min<int64_t>(s->maxc, chunks_new - done);
     const int64_t abs0 = s->nc + done * s->Kc;
-    if (launch_phase(s->alpha_r, s->A, abs0, s->Kc, nch, s->E, st) != hipSuccess ||
-        run_contract(s, v, done * s->Kc, (int64_t)nch * s->Kc, nch, st) != hipSuccess ||
+    if (launch_phase(s->alpha_r, s->A, abs0 + s->dy, s->Kc, nch, s->E, st) != hipSuccess ||
+        run_contract(s, vx, vy, done * s->Kc, (int64_t)nch * s->Kc, nch, st) != hipSuccess ||
         launch_accumulate(s->S, s->part, s->E, s->T, s->A, nch, abs0 == 0 ? 1 : 0, st) != hipSuccess)
       return fail_device(s);
     done += nch;
   }
 
   const int64_t shift = chunks_new * s->Kc;
-  const int64_t n_pend_new = n_pend + n - shift;
-  if (shift == 0) {
-    // append the new samples behind the pending ones
-    VSrc src;
-    src.pend = x;
-    src.xin = nullptr;
-    src.n_pend = n;
-    src.n_avail = n;
-    if (launch_vcopy(src, 0, n, s->pend[s->cur] + n_pend, st) != hipSuccess) return fail_device(s);
-  } else {
-    if (launch_vcopy(v, shift, n_pend_new, s->pend[s->cur ^ 1], st) != hipSuccess)
-      return fail_device(s);
-    s->cur ^= 1;
-  }
+  if (keep_input(s, s->pend, vx, px, sx, s->dx, n, shift, L_new, st) != hipSuccess ||
+      (s->two && keep_input(s, s->pendy, vy, py, sy, s->dy, n, shift, L_new, st) != hipSuccess))
+    return fail_device(s);
+  if (shift > 0) s->cur ^= 1;
   s->L = L_new;
   s->nc += shift;
   return CYC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cyc_push(cyc_state* s, const void* d_x, int64_t n, void* stream) {
+  if (!s || n < 0 || (n > 0 && !d_x)) return CYC_EINVAL;
+  if (s->poisoned) return CYC_ESTATE;
+  if (n == 0) return CYC_OK;
+  const float2* x = reinterpret_cast<const float2*>(d_x);
+  return push_xy(s, x, x, n, as_stream(stream));
+}
+
+int cyc_push2(cyc_state* s, const void* d_x, const void* d_y, int64_t n, void* stream) {
+  if (!s || n < 0 || (n > 0 && (!d_x || !d_y)) || !s->two) return CYC_EINVAL;
+  if (s->poisoned) return CYC_ESTATE;
+  if (n == 0) return CYC_OK;
+  return push_xy(s, reinterpret_cast<const float2*>(d_x), reinterpret_cast<const float2*>(d_y), n,
+                 as_stream(stream));
 }
 
 int cyc_read(cyc_state* s, void* d_R, void* d_Rc, int64_t* n_used, void* stream) {
@@ -365,7 +433,7 @@ int cyc_read(cyc_state* s, void* d_R, void* d_Rc, int64_t* n_used, void* stream)
   hipStream_t st = as_stream(stream);
   const int c128 = (s->flags & CYC_OUT_C128) ? 1 : 0;
   const int64_t tbytes = (int64_t)s->T * s->A * (c128 ? 16 : 8);
-  const int64_t nu = std::max<int64_t>(0, s->L - s->T + 1);
+  const int64_t nu = std::max<int64_t>(0, s->L - (s->T - 1) - s->lagabs);
   if (n_used) *n_used = nu;
   if (!d_R && !d_Rc) return CYC_OK;
   if (nu == 0) {
@@ -376,13 +444,19 @@ int cyc_read(cyc_state* s, void* d_R, void* d_Rc, int64_t* n_used, void* stream)
   }
   const int64_t m = nu - s->nc;  // products of the pending partial chunk, < Kc
   if (m > 0) {
-    VSrc v;
-    v.pend = s->pend[s->cur];
-    v.xin = nullptr;
-    v.n_pend = s->L - s->nc;
-    v.n_avail = v.n_pend;
-    if (launch_phase(s->alpha_r, s->A, s->nc, s->Kc, 1, s->E, st) != hipSuccess ||
-        run_contract(s, v, 0, m, 1, st) != hipSuccess)
+    VSrc vx;
+    vx.pend = s->pend[s->cur];
+    vx.xin = nullptr;
+    vx.n_pend = s->L - s->nc - s->dx;
+    vx.n_avail = vx.n_pend;
+    VSrc vy = vx;
+    if (s->two) {
+      vy.pend = s->pendy[s->cur];
+      vy.n_pend = s->L - s->nc - s->dy;
+      vy.n_avail = vy.n_pend;
+    }
+    if (launch_phase(s->alpha_r, s->A, s->nc + s->dy, s->Kc, 1, s->E, st) != hipSuccess ||
+        run_contract(s, vx, vy, 0, m, 1, st) != hipSuccess)
       return fail_device(s);
   }
   if (launch_finalize(s->S, s->nc > 0 ? 1 : 0, s->part, s->E, m > 0 ? 1 : 0, s->T, s->A, nu, d_R,

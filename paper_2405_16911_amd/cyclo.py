@@ -73,6 +73,10 @@ SIGNATURES = {
                                          ctypes.c_void_p]),
     "cyc_model_gradients": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                            ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "cyc_create2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                   ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p]),
+    "cyc_push2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                 ctypes.c_void_p]),
     "cyc_grid_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_uint32, ctypes.c_void_p]),
     "cyc_grid_push": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
@@ -271,6 +275,30 @@ class CyclicStream:
             self.close()
         except Exception:
             pass
+
+
+class CrossStream(CyclicStream):
+    """Two inputs x, y and lags lag_min .. lag_min + n_lag - 1 (lag m pairs x[k + m] with y[k])."""
+
+    def __init__(self, alphas, lag_min: int, n_lag: int, flags: int = 0, stream=None):
+        self.alphas = np.ascontiguousarray(np.asarray(alphas, dtype=np.float64).reshape(-1))
+        self.T = int(n_lag)
+        self.lag_min = int(lag_min)
+        self.flags = int(flags)
+        out = ctypes.c_void_p()
+        _check(lib().cyc_create2(ctypes.byref(out), self.alphas.ctypes.data_as(ctypes.c_void_p), self.alphas.size,
+                                 self.lag_min, self.T, self.flags, _stream_handle(stream)), "cyc_create2")
+        self._s = out
+
+    def push2(self, x, y, stream=None):
+        import torch
+        for t in (x, y):
+            if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous() or t.dim() != 1:
+                raise ValueError("x and y must be contiguous 1-D complex64 CUDA tensors")
+        if x.numel() != y.numel():
+            raise ValueError("x and y must have the same length")
+        _check(lib().cyc_push2(self._s, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                               int(x.numel()), _stream_handle(stream)), "cyc_push2")
 
 
 # ----------------------------------------------------------------------------- batches

@@ -150,3 +150,14 @@ def test_grid_invalid_arguments(L):
     assert L.cyc_grid_read(None, None, None, None, None) == cyclo.CYC_EINVAL
     assert L.cyc_grid_reset(None) == cyclo.CYC_EINVAL
     L.cyc_grid_destroy(None)
+
+
+def test_two_input_invalid_arguments(L):
+    out = ctypes.c_void_p()
+    a = (ctypes.c_double * 3)(0.0, 0.1, 0.2)
+    assert L.cyc_create2(None, a, 3, -5, 4, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_create2(ctypes.byref(out), a, 3, -(1 << 21), 4, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_create2(ctypes.byref(out), a, 3, 1 << 21, 4, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_create2(ctypes.byref(out), a, 3, -5, 0, 0, None) == cyclo.CYC_EINVAL
+    assert out.value is None
+    assert L.cyc_push2(None, None, None, 0, None) == cyclo.CYC_EINVAL
