@@ -253,6 +253,13 @@ typedef struct cyc_grid cyc_grid;
 int cyc_grid_create(cyc_grid** out, double alpha0, int32_t n_alpha, int32_t n_lag, uint32_t flags,
                     void* stream);
 int cyc_grid_push(cyc_grid* g, const void* d_x, int64_t n, void* stream);
+/* Two inputs and lags lag_min .. lag_min + n_lag - 1 on the uniform grid, with
+ * the conventions of cyc_create2 / cyc_push2 (|lag_min| <= 2^20; cyc_grid_push
+ * on such a state uses x for both inputs; cyc_grid_push2 on a one-input state
+ * returns CYC_EINVAL). */
+int cyc_grid_create2(cyc_grid** out, double alpha0, int32_t n_alpha, int64_t lag_min, int32_t n_lag,
+                     uint32_t flags, void* stream);
+int cyc_grid_push2(cyc_grid* g, const void* d_x, const void* d_y, int64_t n, void* stream);
 int cyc_grid_read(cyc_grid* g, void* d_R, void* d_Rc, int64_t* n_used, void* stream);
 int cyc_grid_reset(cyc_grid* g);
 void cyc_grid_destroy(cyc_grid* g);

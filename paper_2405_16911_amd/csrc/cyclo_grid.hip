@@ -64,11 +64,12 @@ __device__ __forceinline__ float2 gload(const VSrc& v, int64_t g) {
   return g < v.n_pend ? v.pend[g] : v.xin[g - v.n_pend];
 }
 
-// One thread per (fold bin r, group of FOLD_TT lags): q[tab][t][r] += p_t[n] E(n)
-// for the products n = n0 + i, i < np, with n = r (mod A), in ascending n.
-// v holds the samples from absolute index n0 on.
-__global__ __launch_bounds__(FOLD_NT) void grid_fold_kernel(VSrc v, int64_t n0, int64_t np, const double2* E,
-                                                             int T, int A, double2* q) {
+// One thread per (fold bin r, group of FOLD_TT lags): q[tab][t][r] += p_t[i] E[i]
+// for the products i < np whose phase index n0 + i is r (mod A), in ascending i.
+// Product i pairs the leading samples vx[i + t] with the trailing sample vy[i]
+// (the same array for one input); E[i] is its phase.
+__global__ __launch_bounds__(FOLD_NT) void grid_fold_kernel(VSrc vx, VSrc vy, int64_t n0, int64_t np,
+                                                             const double2* E, int T, int A, double2* q) {
   const int r = blockIdx.x * FOLD_NT + threadIdx.x;
   const int t0 = blockIdx.y * FOLD_TT;
   if (r >= A) return;
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(FOLD_NT) void grid_fold_kernel(VSrc v, int64_t n0, 
     }
   }
   for (; i < np; i += A) {
-    const float2 x0 = gload(v, i);
+    const float2 x0 = gload(vy, i);
     const double2 e = E[i];
     const double2 xc = make_double2((double)x0.x, -(double)x0.y);  // conj(x[n])
     const double2 xn = make_double2((double)x0.x, (double)x0.y);
@@ -96,7 +97,7 @@ __global__ __launch_bounds__(FOLD_NT) void grid_fold_kernel(VSrc v, int64_t n0, 
 #pragma unroll
     for (int k = 0; k < FOLD_TT; ++k) {
       if (k < nt) {
-        const float2 xl = gload(v, i + t0 + k);
+        const float2 xl = gload(vx, i + t0 + k);
         const double2 a = make_double2((double)xl.x, (double)xl.y);
         const double2 p0 = cmul(a, ec), p1 = cmul(a, en);
         acc[0][k].x += p0.x;
@@ -227,8 +228,11 @@ struct cyc_grid {
   double2* Y = nullptr;
   double2* tw = nullptr;
   double2* E = nullptr;
-  float2* pend[2] = {nullptr, nullptr};
+  float2* pend[2] = {nullptr, nullptr};   // leading input x, from absolute index nc + dx
+  float2* pendy[2] = {nullptr, nullptr};  // trailing input y, from nc + dy (two inputs)
   int cur = 0;
+  bool two = false;
+  int64_t dx = 0, dy = 0, lagabs = 0;
   bool poisoned = false;
 };
 
@@ -242,6 +246,8 @@ void grid_free(cyc_grid* g) {
   (void)hipFree(g->E);
   (void)hipFree(g->pend[0]);
   (void)hipFree(g->pend[1]);
+  (void)hipFree(g->pendy[0]);
+  (void)hipFree(g->pendy[1]);
   delete g;
 }
 
@@ -259,8 +265,10 @@ int grid_fail(cyc_grid* g) {
 
 extern "C" {
 
-int cyc_grid_create(cyc_grid** out, double alpha0, int32_t n_alpha, int32_t n_lag, uint32_t flags, void* stream) {
+static int grid_create(cyc_grid** out, double alpha0, int32_t n_alpha, int64_t lag_min, int32_t n_lag,
+                       uint32_t flags, bool two, void* stream) {
   if (!out || n_lag < 1 || n_lag > 4096 || !std::isfinite(alpha0)) return CYC_EINVAL;
+  if (lag_min < -(1 << 20) || lag_min > (1 << 20)) return CYC_EINVAL;
   if (flags & ~CYC_OUT_C128) return CYC_EINVAL;
   if (n_alpha < 2 || n_alpha > 65536 || (n_alpha & (n_alpha - 1)) != 0) return CYC_EUNSUPPORTED;
   cyc_grid* g = new (std::nothrow) cyc_grid();
@@ -270,10 +278,16 @@ int cyc_grid_create(cyc_grid** out, double alpha0, int32_t n_alpha, int32_t n_la
   while ((1 << g->logA) < n_alpha) ++g->logA;
   g->flags = flags;
   g->alpha0 = alpha0 - std::nearbyint(alpha0);
+  g->two = two;
+  g->dx = std::max<int64_t>(0, lag_min);
+  g->dy = std::max<int64_t>(0, -lag_min);
+  g->lagabs = lag_min < 0 ? -lag_min : lag_min;
+  const int64_t PC = (int64_t)g->T + g->lagabs;  // pending samples of either input
   const int64_t TA2 = 2 * (int64_t)g->T * g->A;
   if (galloc(&g->q, TA2) != hipSuccess || galloc(&g->tw, g->A) != hipSuccess ||
-      galloc(&g->E, MAXP) != hipSuccess || galloc(&g->pend[0], g->T) != hipSuccess ||
-      galloc(&g->pend[1], g->T) != hipSuccess ||
+      galloc(&g->E, MAXP) != hipSuccess || galloc(&g->pend[0], PC) != hipSuccess ||
+      galloc(&g->pend[1], PC) != hipSuccess ||
+      (two && (galloc(&g->pendy[0], PC) != hipSuccess || galloc(&g->pendy[1], PC) != hipSuccess)) ||
       (g->A > FFT_MAX && galloc(&g->Y, TA2) != hipSuccess)) {
     grid_free(g);
     return CYC_ENOMEM;
@@ -289,52 +303,94 @@ int cyc_grid_create(cyc_grid** out, double alpha0, int32_t n_alpha, int32_t n_la
   return CYC_OK;
 }
 
-int cyc_grid_push(cyc_grid* g, const void* d_x, int64_t n, void* stream) {
-  if (!g || n < 0 || (n > 0 && !d_x)) return CYC_EINVAL;
-  if (g->poisoned) return CYC_ESTATE;
-  if (n == 0) return CYC_OK;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const float2* x = reinterpret_cast<const float2*>(d_x);
-  const int64_t L_new = g->L + n;
-  const int64_t nu_new = std::max<int64_t>(0, L_new - g->T + 1);
-  const int64_t np = nu_new - g->nc;  // products that now have all their samples
+int cyc_grid_create(cyc_grid** out, double alpha0, int32_t n_alpha, int32_t n_lag, uint32_t flags, void* stream) {
+  return grid_create(out, alpha0, n_alpha, 0, n_lag, flags, false, stream);
+}
+
+int cyc_grid_create2(cyc_grid** out, double alpha0, int32_t n_alpha, int64_t lag_min, int32_t n_lag,
+                     uint32_t flags, void* stream) {
+  return grid_create(out, alpha0, n_alpha, lag_min, n_lag, flags, true, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// One input's virtual array for a push: pending samples from absolute index
+// nc + d, then the part of the new block from that index on.
+VSrc grid_src(const cyc_grid* g, float2* const* bufs, int64_t d, const float2* blk, int64_t n) {
+  const int64_t n_pend = std::max<int64_t>(0, g->L - (g->nc + d));
+  const int64_t skip = std::min<int64_t>(n, std::max<int64_t>(0, g->nc + d - g->L));
   VSrc v;
-  v.pend = g->pend[g->cur];
-  v.xin = x;
-  v.n_pend = g->L - g->nc;
-  v.n_avail = v.n_pend + n;
+  v.pend = bufs[g->cur];
+  v.xin = blk + skip;
+  v.n_pend = n_pend;
+  v.n_avail = n_pend + (n - skip);
+  return v;
+}
+
+int grid_push_xy(cyc_grid* g, const float2* x, const float2* y, int64_t n, hipStream_t st) {
+  const int64_t L_new = g->L + n;
+  const int64_t nu_new = std::max<int64_t>(0, L_new - (g->T - 1) - g->lagabs);
+  const int64_t np = nu_new - g->nc;  // products that now have all their samples
+  const VSrc vx = grid_src(g, g->pend, g->dx, x, n);
+  const VSrc vy = g->two ? grid_src(g, g->pendy, g->dy, y, n) : vx;
   const dim3 fgrid(nblk(g->A, FOLD_NT), (unsigned)((g->T + FOLD_TT - 1) / FOLD_TT));
+  auto shifted = [](VSrc v, int64_t k) {  // the same array from element k on
+    if (k < v.n_pend) {
+      v.pend += k;
+      v.n_pend -= k;
+    } else {
+      v.xin += k - v.n_pend;
+      v.pend = v.xin;
+      v.n_pend = 0;
+    }
+    v.n_avail -= k;
+    return v;
+  };
   for (int64_t done = 0; done < np;) {
     const int64_t m = std::min<int64_t>(MAXP, np - done);
-    VSrc vs = v;  // samples from absolute index nc + done on
-    if (done > 0) {
-      // shift the virtual array by `done` samples
-      if (done < vs.n_pend) {
-        vs.pend += done;
-        vs.n_pend -= done;
-      } else {
-        vs.xin += done - vs.n_pend;
-        vs.pend = vs.xin;
-        vs.n_pend = 0;
-      }
-      vs.n_avail -= done;
-    }
-    hipLaunchKernelGGL(grid_phase_kernel, dim3(nblk(m)), dim3(256), 0, st, g->alpha0, g->nc + done, m, g->E);
-    hipLaunchKernelGGL(grid_fold_kernel, fgrid, dim3(FOLD_NT), 0, st, vs, g->nc + done, m, g->E, g->T, g->A,
-                       g->q);
+    const VSrc sx = done > 0 ? shifted(vx, done) : vx;
+    const VSrc sy = done > 0 ? shifted(vy, done) : vy;
+    hipLaunchKernelGGL(grid_phase_kernel, dim3(nblk(m)), dim3(256), 0, st, g->alpha0, g->nc + done + g->dy, m,
+                       g->E);
+    // the phase and the fold bin follow y's index: product n goes to bin (n + dy) mod A
+    hipLaunchKernelGGL(grid_fold_kernel, fgrid, dim3(FOLD_NT), 0, st, sx, sy, g->nc + done + g->dy, m, g->E, g->T,
+                       g->A, g->q);
     if (hipGetLastError() != hipSuccess) return grid_fail(g);
     done += m;
   }
-  // keep the samples from the new first unfolded product on (< T of them)
-  const int64_t keep = L_new - nu_new;
-  if (keep > 0) {
-    hipLaunchKernelGGL(grid_copy_kernel, dim3(nblk(keep)), dim3(256), 0, st, v, np, keep, g->pend[g->cur ^ 1]);
-    if (hipGetLastError() != hipSuccess) return grid_fail(g);
-  }
+  // keep each input's samples from nu_new + d on (fewer than T + |lag_min|)
+  const int64_t kx = L_new - (nu_new + g->dx), ky = L_new - (nu_new + g->dy);
+  if (kx > 0)
+    hipLaunchKernelGGL(grid_copy_kernel, dim3(nblk(kx)), dim3(256), 0, st, vx, np, kx, g->pend[g->cur ^ 1]);
+  if (g->two && ky > 0)
+    hipLaunchKernelGGL(grid_copy_kernel, dim3(nblk(ky)), dim3(256), 0, st, vy, np, ky, g->pendy[g->cur ^ 1]);
+  if (hipGetLastError() != hipSuccess) return grid_fail(g);
   g->cur ^= 1;
   g->L = L_new;
   g->nc = nu_new;
   return CYC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cyc_grid_push(cyc_grid* g, const void* d_x, int64_t n, void* stream) {
+  if (!g || n < 0 || (n > 0 && !d_x)) return CYC_EINVAL;
+  if (g->poisoned) return CYC_ESTATE;
+  if (n == 0) return CYC_OK;
+  const float2* x = reinterpret_cast<const float2*>(d_x);
+  return grid_push_xy(g, x, x, n, reinterpret_cast<hipStream_t>(stream));
+}
+
+int cyc_grid_push2(cyc_grid* g, const void* d_x, const void* d_y, int64_t n, void* stream) {
+  if (!g || n < 0 || (n > 0 && (!d_x || !d_y)) || !g->two) return CYC_EINVAL;
+  if (g->poisoned) return CYC_ESTATE;
+  if (n == 0) return CYC_OK;
+  return grid_push_xy(g, reinterpret_cast<const float2*>(d_x), reinterpret_cast<const float2*>(d_y), n,
+                      reinterpret_cast<hipStream_t>(stream));
 }
 
 int cyc_grid_read(cyc_grid* g, void* d_R, void* d_Rc, int64_t* n_used, void* stream) {

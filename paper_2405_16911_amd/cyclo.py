@@ -79,6 +79,10 @@ SIGNATURES = {
                                  ctypes.c_void_p]),
     "cyc_grid_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_uint32, ctypes.c_void_p]),
+    "cyc_grid_create2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int64,
+                                        ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p]),
+    "cyc_grid_push2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_void_p]),
     "cyc_grid_push": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "cyc_grid_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
@@ -403,12 +407,28 @@ class CyclicBatch:
 class GridStream:
     """Tables on the whole grid alpha_k = alpha0 + k / n_alpha by fold and FFT (n_alpha a power of two)."""
 
-    def __init__(self, alpha0: float, n_alpha: int, n_lag: int, flags: int = 0, stream=None):
+    def __init__(self, alpha0: float, n_alpha: int, n_lag: int, flags: int = 0, stream=None, lag_min=None):
+        """lag_min given: two inputs (push2) and lags lag_min .. lag_min + n_lag - 1."""
         self.alpha0, self.A, self.T, self.flags = float(alpha0), int(n_alpha), int(n_lag), int(flags)
+        self.lag_min = lag_min
         out = ctypes.c_void_p()
-        _check(lib().cyc_grid_create(ctypes.byref(out), self.alpha0, self.A, self.T, self.flags,
-                                     _stream_handle(stream)), "cyc_grid_create")
+        if lag_min is None:
+            _check(lib().cyc_grid_create(ctypes.byref(out), self.alpha0, self.A, self.T, self.flags,
+                                         _stream_handle(stream)), "cyc_grid_create")
+        else:
+            _check(lib().cyc_grid_create2(ctypes.byref(out), self.alpha0, self.A, int(lag_min), self.T, self.flags,
+                                          _stream_handle(stream)), "cyc_grid_create2")
         self._g = out
+
+    def push2(self, x, y, stream=None):
+        import torch
+        for t in (x, y):
+            if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("x and y must be contiguous complex64 CUDA tensors")
+        if x.numel() != y.numel():
+            raise ValueError("x and y must have the same length")
+        _check(lib().cyc_grid_push2(self._g, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                    int(x.numel()), _stream_handle(stream)), "cyc_grid_push2")
 
     @property
     def alphas(self) -> np.ndarray:

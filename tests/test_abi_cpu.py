@@ -161,3 +161,7 @@ def test_two_input_invalid_arguments(L):
     assert L.cyc_create2(ctypes.byref(out), a, 3, -5, 0, 0, None) == cyclo.CYC_EINVAL
     assert out.value is None
     assert L.cyc_push2(None, None, None, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_grid_create2(None, 0.0, 64, -3, 4, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_grid_create2(ctypes.byref(out), 0.0, 64, 1 << 21, 4, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_grid_create2(ctypes.byref(out), 0.0, 100, -3, 4, 0, None) == cyclo.CYC_EUNSUPPORTED
+    assert L.cyc_grid_push2(None, None, None, 0, None) == cyclo.CYC_EINVAL

@@ -139,3 +139,30 @@ def test_invalid_arguments(cy):
         cy.GridStream(0.0, 1 << 17, 4)   # too large
     with pytest.raises(cy.CycloError):
         cy.GridStream(float("nan"), 64, 4)
+
+
+@pytest.mark.parametrize("lag_min,T,A", [(-9, 20, 512), (4, 6, 128), (-300, 8, 16384)])
+def test_two_inputs_match_the_cross_oracle(cy, lag_min, T, A):
+    from oracle.cyclic import cross_tables
+    L = 9000 + abs(lag_min)
+    x = siggen.qpsk_rrc_stream(n=L, seed=21)
+    y = (np.roll(x, 5) + 0.5 * siggen.gmsk_stream(n=L, seed=22)).astype(np.complex64)
+    alpha0 = -0.5
+    ks = np.arange(A) if A <= 512 else np.unique(np.concatenate([[0, A // 2, A - 1],
+                                                                  np.random.default_rng(A).integers(0, A, 30)]))
+    Ro, Rco, no = cross_tables(x, y, alpha0 + ks / A, lag_min, T)
+    g = cy.GridStream(alpha0, A, T, cy.CYC_OUT_C128, lag_min=lag_min)
+    dx, dy = torch.from_numpy(x).to("cuda"), torch.from_numpy(y).to("cuda")
+    for a, b in ((0, 1), (1, 333), (333, 4000), (4000, L)):
+        g.push2(dx[a:b], dy[a:b])
+    R, Rc, n = g.read()
+    torch.cuda.synchronize()
+    g.close()
+    assert n == no
+    R, Rc = R.cpu().numpy()[:, ks], Rc.cpu().numpy()[:, ks]
+    ax, ay = np.abs(x.astype(np.complex128)), np.abs(y.astype(np.complex128))
+    dxo, dyo = max(0, lag_min), max(0, -lag_min)
+    sc = np.array([np.mean(ax[dxo + t: dxo + t + n] * ay[dyo: dyo + n]) for t in range(T)])[:, None]
+    e = max(np.max(np.abs(R - Ro) / sc), np.max(np.abs(Rc - Rco) / sc))
+    print(f"  two inputs lag_min={lag_min} A={A}: max scaled error {e:.2e}", flush=True)
+    assert e <= TOL
