@@ -265,6 +265,26 @@ int cyc_grid_reset(cyc_grid* g);
 void cyc_grid_destroy(cyc_grid* g);
 
 /*
+ * Cyclic spectrum from a lag table, by the cyclic Wiener-Khinchin relation
+ * (the paper leaves spectral analysis of the cyclic statistics for future
+ * work, Sec. 6):
+ *   S[k][a] = sum_{t<n_lag} w(m_t) exp(-j pi alpha_a m_t) R[t][a] exp(-j2pi f_k m_t),
+ *   m_t = lag_min + t,  f_k = -1/2 + k / n_freq,  k < n_freq.
+ * exp(-j pi alpha m) R(m) is the symmetric form of the leading-lag tables this
+ * library returns (either table, from cyc_read / cyc_grid_read, lags of
+ * either sign from the two-input states).  window: 0 rectangular, 1 Hann,
+ * w(m) = (1 + cos(pi m / (M + 1))) / 2 with M = max |m_t|.
+ *   d_R      complex64 [n_lag][n_alpha] device table; d_alphas FP64 [n_alpha]
+ *            device array of its cycle frequencies;
+ *   d_S      complex64 [n_freq][n_alpha] device output.
+ * FP64 phases, FP32 sums.  n_lag <= 8192, n_freq <= 65536, |lag_min| <= 2^20.
+ * A workspace of 8 n_lag n_alpha bytes is allocated stream-ordered.  Errors:
+ * CYC_EINVAL, CYC_ENOMEM, CYC_EDEVICE.
+ */
+int cyc_scf(const void* d_R, const double* d_alphas, int32_t n_alpha, int64_t lag_min, int32_t n_lag,
+            int32_t n_freq, int32_t window, void* d_S, void* stream);
+
+/*
  * Learned cycle-frequency proposal (coarse stage of a coarse-to-fine
  * estimator; the paper's related work in Sec. 1 describes the two-stage idea
  * and Sec. 6 names cycle-frequency estimation as future work).

@@ -207,6 +207,35 @@ def cross_tables(x, y, alphas, lag_min: int, T: int):
     return (X * np.conj(yb)[None, :]) @ E / N, (X * yb[None, :]) @ E / N, N
 
 
+def lag_window(lags, window: str):
+    """Lag window: 'rect' (ones) or 'hann', w(m) = (1 + cos(pi m / (M + 1))) / 2 with M = max |m|."""
+    lags = np.asarray(lags, dtype=np.float64)
+    if window == "rect":
+        return np.ones_like(lags)
+    M = np.max(np.abs(lags))
+    return 0.5 * (1.0 + np.cos(np.pi * lags / (M + 1.0)))
+
+
+def cyclic_spectrum(R, alphas, lag_min: int, n_freq: int, window: str = "rect"):
+    """Cyclic spectrum by the cyclic Wiener-Khinchin relation, from a table R[t, a]
+    with lags m_t = lag_min + t (as cross_tables or the single-input tables):
+
+      S[k, a] = sum_t w(m_t) exp(-j pi alpha_a m_t) R[t, a] exp(-j2pi f_k m_t),
+      f_k = -1/2 + k / n_freq.
+
+    exp(-j pi alpha m) R(m) is the symmetric form sum x[k + m/2] conj(y[k - m/2])
+    exp(-j2pi alpha k) of the leading-lag table.  Plain definition in FP64.
+    """
+    R = np.asarray(R, dtype=np.complex128)
+    T, A = R.shape
+    m = lag_min + np.arange(T)
+    al = np.asarray(alphas, dtype=np.float64).reshape(-1)
+    f = -0.5 + np.arange(n_freq) / n_freq
+    w = lag_window(m, window)
+    P = w[:, None] * np.exp(-1j * np.pi * al[None, :] * m[:, None]) * R
+    return np.exp(-2j * np.pi * f[:, None] * m[None, :]) @ P
+
+
 def cyclic_cell(x, alpha: float, tau: int, T: int, n_block: int = 1 << 20):
     """O1: one (alpha, tau) cell of (R, Rc) by a direct dot product over n.
 

@@ -88,6 +88,8 @@ SIGNATURES = {
                                      ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
     "cyc_grid_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "cyc_grid_destroy": (None, [ctypes.c_void_p]),
+    "cyc_scf": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                               ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "cyc_propose": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -469,6 +471,21 @@ class GridStream:
             self.close()
         except Exception:
             pass
+
+
+def cyc_scf(R, alphas, lag_min: int, n_freq: int, window: str = "rect", stream=None):
+    """Cyclic spectrum [n_freq, A] (complex64, GPU) of a complex64 [T, A] lag table R on the GPU."""
+    import torch
+    if R.dtype != torch.complex64 or not R.is_cuda or not R.is_contiguous() or R.dim() != 2:
+        raise ValueError("R must be a contiguous complex64 [T, A] CUDA tensor")
+    T, A = R.shape
+    al = torch.as_tensor(np.asarray(alphas, dtype=np.float64).reshape(-1), device=R.device)
+    if al.numel() != A:
+        raise ValueError("one cycle frequency per column")
+    S = torch.empty((int(n_freq), A), dtype=torch.complex64, device=R.device)
+    _check(lib().cyc_scf(_p(R), _p(al), A, int(lag_min), T, int(n_freq), {"rect": 0, "hann": 1}[window], _p(S),
+                         _stream_handle(stream)), "cyc_scf")
+    return S
 
 
 # ----------------------------------------------------------------------------- learned proposal

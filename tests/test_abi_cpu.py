@@ -165,3 +165,7 @@ def test_two_input_invalid_arguments(L):
     assert L.cyc_grid_create2(ctypes.byref(out), 0.0, 64, 1 << 21, 4, 0, None) == cyclo.CYC_EINVAL
     assert L.cyc_grid_create2(ctypes.byref(out), 0.0, 100, -3, 4, 0, None) == cyclo.CYC_EUNSUPPORTED
     assert L.cyc_grid_push2(None, None, None, 0, None) == cyclo.CYC_EINVAL
+
+
+def test_scf_invalid_arguments(L):
+    assert L.cyc_scf(None, None, 4, 0, 4, 16, 0, None, None) == cyclo.CYC_EINVAL
