@@ -119,6 +119,23 @@ int cyc_create2(cyc_state** out, const double* alphas_host, int32_t n_alpha, int
 int cyc_push2(cyc_state* s, const void* d_x, const void* d_y, int64_t n, void* stream);
 
 /*
+ * Sliding-window form (the block of Sec. 4 emits the estimate over a window
+ * of its latest samples, the phase re-referenced to the window's start by
+ * its `state`).  Products are committed in hops of `hop` (aligned to the
+ * first product); cyc_read returns the estimate over the last
+ * W = min(n_hops, complete hops) hops, products n_w .. n_w + W hop - 1:
+ *   R[t][a] = (1/(W hop)) sum_n x[n+t] conj(x[n]) exp(-j2pi frac(alpha_a (n - n_w)))
+ * (and Rc alike), *n_used = W hop (zero tables before the first complete
+ * hop; products of an incomplete hop are not part of any window yet).
+ * hop: a multiple of 32 in [32, 2^20]; n_hops in [1, 4096]; the other
+ * arguments as cyc_create.  push / read / reset / destroy are the
+ * single-input calls; results do not depend on how samples are pushed.
+ * Memory: 32 n_hops T A bytes for the window's FP64 hop sums.
+ */
+int cyc_create_window(cyc_state** out, const double* alphas_host, int32_t n_alpha, int32_t n_lag,
+                      int32_t hop, int32_t n_hops, uint32_t flags, void* stream);
+
+/*
  * Forget every pushed sample and clear the poison flag; alphas, T and flags
  * are kept.  Afterwards the state behaves exactly like a fresh one.  Host-only
  * (enqueues no device work).  Errors: CYC_EINVAL (s NULL).

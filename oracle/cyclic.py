@@ -207,6 +207,32 @@ def cross_tables(x, y, alphas, lag_min: int, T: int):
     return (X * np.conj(yb)[None, :]) @ E / N, (X * yb[None, :]) @ E / N, N
 
 
+def window_tables(x, alphas, T: int, hop: int, n_hops: int):
+    """Sliding-window form: the estimate over the last n_hops complete hops.
+
+    Products are grouped in hops of `hop` (aligned to the first product); with
+    c complete hops among the N = L - T + 1 products, the window holds the
+    last W = min(n_hops, c) of them, products n_w .. n_w + W hop - 1 with
+    n_w = (c - W) hop, and the phase is referenced to the window's first
+    product (as the block's `state` re-references it, Sec. 4):
+      R[t, a] = (1/(W hop)) sum_{n in window} x[n+t] conj(x[n]) E(a, n - n_w),
+    i.e. the cumulative tables of the slice x[n_w : n_w + W hop + T - 1].
+    Returns (R, Rc, W hop) (zero tables and 0 before the first complete hop).
+    """
+    x = np.asarray(x).astype(np.complex128).reshape(-1)
+    N = max(0, x.size - T + 1)
+    c = N // hop
+    W = min(n_hops, c)
+    if W == 0:
+        A = len(_Alphas(alphas, None))
+        z = np.zeros((T, A), dtype=np.complex128)
+        return z, z.copy(), 0
+    n_w = (c - W) * hop
+    R, Rc, n = cyclic_tables(x[n_w: n_w + W * hop + T - 1], alphas, T)
+    assert n == W * hop
+    return R, Rc, n
+
+
 def lag_window(lags, window: str):
     """Lag window: 'rect' (ones) or 'hann', w(m) = (1 + cos(pi m / (M + 1))) / 2 with M = max |m|."""
     lags = np.asarray(lags, dtype=np.float64)

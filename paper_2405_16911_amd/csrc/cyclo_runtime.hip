@@ -30,6 +30,13 @@
 
 using namespace cyclo;
 
+namespace cyclo {
+hipError_t launch_window_store(double2* ring, const float2* part, const double2* E, int T, int A, int nc,
+                               int64_t c0, int W, hipStream_t st);
+hipError_t launch_window_finalize(const double2* ring, int W, int s0, int Wn, int T, int A, const double* alpha_r,
+                                  int64_t n_ref, int64_t n_used, void* R, void* Rc, int c128, hipStream_t st);
+}  // namespace cyclo
+
 struct cyc_state {
   int T = 0, A = 0;
   uint32_t flags = 0;
@@ -46,6 +53,8 @@ struct cyc_state {
   bool two = false;              // two inputs (cyc_create2)
   int64_t lag_min = 0, dx = 0, dy = 0, lagabs = 0;
   int64_t PC = 0;                // pending capacity (samples)
+  int win = 0;                   // sliding window: hops per window (0: cumulative)
+  double2* ring = nullptr;       // [win][2][T][A] FP64 contribution of each hop in the window
   float2* part = nullptr;
   double2* E = nullptr;
   int64_t L = 0;
@@ -177,6 +186,7 @@ void free_state(cyc_state* s) {
   (void)hipFree(s->pendy[0]);
   (void)hipFree(s->pendy[1]);
   (void)hipFree(s->part);
+  (void)hipFree(s->ring);
   (void)hipFree(s->E);
   delete s;
 }
@@ -247,8 +257,10 @@ const char* cyc_status_str(int code) {
 }
 
 static int create_state(cyc_state** out, const double* alphas_host, int32_t n_alpha, int64_t lag_min,
-                        int32_t n_lag, uint32_t flags, bool two, void* stream) {
+                        int32_t n_lag, uint32_t flags, bool two, int32_t hop, int32_t n_hops, void* stream) {
   if (!out || !alphas_host || n_alpha < 1 || n_lag < 1 || n_lag > kMaxLag) return CYC_EINVAL;
+  if (n_hops < 0 || n_hops > 4096 || (n_hops > 0 && (hop < 32 || hop > (1 << 20) || hop % 32 != 0)))
+    return CYC_EINVAL;
   if (lag_min < -kMaxLagShift || lag_min > kMaxLagShift) return CYC_EINVAL;
   if (flags & ~(CYC_OP_MASK | CYC_TW_SPLIT | CYC_OUT_C128)) return CYC_EINVAL;
   const int prec = (int)(flags & CYC_OP_MASK);
@@ -280,11 +292,12 @@ static int create_state(cyc_state** out, const double* alphas_host, int32_t n_al
   // (alpha tiles x chunks), so a single stream keeps 4096 for every operand
   // precision; batches take longer 16-bit chunks because their streams
   // supply the parallelism.
-  int64_t kc = env_i64("CYC_CHUNK", 4096);
+  int64_t kc = n_hops > 0 ? hop : env_i64("CYC_CHUNK", 4096);
   kc = std::max<int64_t>(cfg.ks, std::min<int64_t>(kc, 1 << 20));
   kc = (kc / cfg.ks) * cfg.ks;
   s->Kc = (int)kc;
   s->nsteps = s->Kc / s->KS;
+  s->win = n_hops;
   // pending samples of either input: < Kc products plus T - 1 + |lag_min| samples
   s->PC = (int64_t)s->Kc + s->T + s->lagabs;
 
@@ -309,6 +322,7 @@ static int create_state(cyc_state** out, const double* alphas_host, int32_t n_al
       (two && (dalloc(&s->pendy[0], (size_t)s->PC) != hipSuccess ||
                dalloc(&s->pendy[1], (size_t)s->PC) != hipSuccess)) ||
       dalloc(&s->part, (size_t)s->maxc * TA2) != hipSuccess ||
+      (s->win > 0 && dalloc(&s->ring, (size_t)s->win * TA2) != hipSuccess) ||
       dalloc(&s->E, (size_t)s->maxc * s->A) != hipSuccess) {
     rc = CYC_ENOMEM;
   }
@@ -330,12 +344,18 @@ static int create_state(cyc_state** out, const double* alphas_host, int32_t n_al
 
 int cyc_create(cyc_state** out, const double* alphas_host, int32_t n_alpha, int32_t n_lag,
                uint32_t flags, void* stream) {
-  return create_state(out, alphas_host, n_alpha, 0, n_lag, flags, false, stream);
+  return create_state(out, alphas_host, n_alpha, 0, n_lag, flags, false, 0, 0, stream);
+}
+
+int cyc_create_window(cyc_state** out, const double* alphas_host, int32_t n_alpha, int32_t n_lag, int32_t hop,
+                      int32_t n_hops, uint32_t flags, void* stream) {
+  if (n_hops < 1) return CYC_EINVAL;
+  return create_state(out, alphas_host, n_alpha, 0, n_lag, flags, false, hop, n_hops, stream);
 }
 
 int cyc_create2(cyc_state** out, const double* alphas_host, int32_t n_alpha, int64_t lag_min, int32_t n_lag,
                 uint32_t flags, void* stream) {
-  return create_state(out, alphas_host, n_alpha, lag_min, n_lag, flags, true, stream);
+  return create_state(out, alphas_host, n_alpha, lag_min, n_lag, flags, true, 0, 0, stream);
 }
 
 }  // extern "C"
@@ -392,7 +412,8 @@ int push_xy(cyc_state* s, const float2* x, const float2* y, int64_t n, hipStream
     const int64_t abs0 = s->nc + done * s->Kc;
     if (launch_phase(s->alpha_r, s->A, abs0 + s->dy, s->Kc, nch, s->E, st) != hipSuccess ||
         run_contract(s, vx, vy, done * s->Kc, (int64_t)nch * s->Kc, nch, st) != hipSuccess ||
-        launch_accumulate(s->S, s->part, s->E, s->T, s->A, nch, abs0 == 0 ? 1 : 0, st) != hipSuccess)
+        (s->win > 0 ? launch_window_store(s->ring, s->part, s->E, s->T, s->A, nch, abs0 / s->Kc, s->win, st)
+                    : launch_accumulate(s->S, s->part, s->E, s->T, s->A, nch, abs0 == 0 ? 1 : 0, st)) != hipSuccess)
       return fail_device(s);
     done += nch;
   }
@@ -433,6 +454,25 @@ int cyc_read(cyc_state* s, void* d_R, void* d_Rc, int64_t* n_used, void* stream)
   hipStream_t st = as_stream(stream);
   const int c128 = (s->flags & CYC_OUT_C128) ? 1 : 0;
   const int64_t tbytes = (int64_t)s->T * s->A * (c128 ? 16 : 8);
+  if (s->win > 0) {
+    // the last min(win, hops committed) complete hops, phase from the window's first product
+    const int64_t hops = s->nc / s->Kc;
+    const int Wn = (int)std::min<int64_t>(s->win, hops);
+    const int64_t nw = (int64_t)Wn * s->Kc;
+    if (n_used) *n_used = nw;
+    if (!d_R && !d_Rc) return CYC_OK;
+    if (Wn == 0) {
+      if ((d_R && launch_zero(d_R, tbytes, st) != hipSuccess) ||
+          (d_Rc && launch_zero(d_Rc, tbytes, st) != hipSuccess))
+        return fail_device(s);
+      return CYC_OK;
+    }
+    const int64_t first = hops - Wn;
+    if (launch_window_finalize(s->ring, s->win, (int)(first % s->win), Wn, s->T, s->A, s->alpha_r,
+                               first * s->Kc + s->dy, nw, d_R, d_Rc, c128, st) != hipSuccess)
+      return fail_device(s);
+    return CYC_OK;
+  }
   const int64_t nu = std::max<int64_t>(0, s->L - (s->T - 1) - s->lagabs);
   if (n_used) *n_used = nu;
   if (!d_R && !d_Rc) return CYC_OK;

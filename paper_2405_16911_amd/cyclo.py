@@ -75,6 +75,8 @@ SIGNATURES = {
                                            ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "cyc_create2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                                    ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p]),
+    "cyc_create_window": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p]),
     "cyc_push2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                  ctypes.c_void_p]),
     "cyc_grid_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
@@ -305,6 +307,19 @@ class CrossStream(CyclicStream):
             raise ValueError("x and y must have the same length")
         _check(lib().cyc_push2(self._s, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                int(x.numel()), _stream_handle(stream)), "cyc_push2")
+
+
+class WindowStream(CyclicStream):
+    """Estimate over the last n_hops complete hops of `hop` products (phase from the window start)."""
+
+    def __init__(self, alphas, n_lag: int, hop: int, n_hops: int, flags: int = 0, stream=None):
+        self.alphas = np.ascontiguousarray(np.asarray(alphas, dtype=np.float64).reshape(-1))
+        self.T, self.hop, self.n_hops, self.flags = int(n_lag), int(hop), int(n_hops), int(flags)
+        out = ctypes.c_void_p()
+        _check(lib().cyc_create_window(ctypes.byref(out), self.alphas.ctypes.data_as(ctypes.c_void_p),
+                                       self.alphas.size, self.T, self.hop, self.n_hops, self.flags,
+                                       _stream_handle(stream)), "cyc_create_window")
+        self._s = out
 
 
 # ----------------------------------------------------------------------------- batches

@@ -169,3 +169,13 @@ def test_two_input_invalid_arguments(L):
 
 def test_scf_invalid_arguments(L):
     assert L.cyc_scf(None, None, 4, 0, 4, 16, 0, None, None) == cyclo.CYC_EINVAL
+
+
+def test_window_invalid_arguments(L):
+    out = ctypes.c_void_p()
+    a = (ctypes.c_double * 3)(0.0, 0.1, 0.2)
+    assert L.cyc_create_window(ctypes.byref(out), a, 3, 4, 64, 0, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_create_window(ctypes.byref(out), a, 3, 4, 48, 4, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_create_window(ctypes.byref(out), a, 3, 4, 0, 4, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_create_window(ctypes.byref(out), a, 3, 4, 64, 5000, 0, None) == cyclo.CYC_EINVAL
+    assert out.value is None
