@@ -377,8 +377,9 @@ int cyc_propose(cyc_model* m, const void* d_x, int32_t n_windows, int32_t topk, 
  * median of |R[t][.]| over the fine bins of coarse bins c-1, c, c+1 (circular)
  * divided by sqrt(2 ln 2), the Rayleigh scale of noise-only cells (an even
  * count takes the mean of the two middle magnitudes).  The non-conjugate
- * table is ignored in zero_bin (-1 for none).  Magnitudes and the threshold
- * are FP64.  Requires 3 * n_alpha / n_coarse <= 1024 and n_lag <= 65535.
+ * table is ignored in zero_bin (-1 for none).  Either table may be NULL (it
+ * contributes no peaks), not both.  Magnitudes and the threshold are FP64.
+ * Requires 3 * n_alpha / n_coarse <= 1024 and n_lag <= 65535.
  * A workspace of 16 * n_lag * n_coarse bytes is allocated stream-ordered.
  */
 int cyc_peak_labels(const void* d_R, const void* d_Rc, int32_t n_lag, int32_t n_alpha,

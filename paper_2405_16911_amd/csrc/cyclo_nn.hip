@@ -260,19 +260,36 @@ __global__ void relu_bwd_kernel(float* d, const float* u, int64_t n) {
   if (i < n && !(u[i] > 0.f)) d[i] = 0.f;
 }
 
-// out[r] = sum_j X[r][j] (one block per row, fixed reduction order)
-__global__ void rowsum_kernel(const float* X, float* out, int64_t ncol) {
+// Row sums in two fixed-order passes: part[r][s] = sum over slice s of the
+// columns of X[r][j] (times Y[j] when Y is given), then out[r] = sum_s part[r][s].
+constexpr int RSPLIT = 64;
+
+__global__ __launch_bounds__(256) void rowsum_part_kernel(const float* X, const float* Y, float* part,
+                                                          int64_t ncol) {
   __shared__ float red[256];
-  const int r = blockIdx.x;
+  const int r = blockIdx.x, sl = blockIdx.y;
+  const int64_t len = (ncol + RSPLIT - 1) / RSPLIT;
+  const int64_t j0 = sl * len, j1 = j0 + len < ncol ? j0 + len : ncol;
   float s = 0.f;
-  for (int64_t j = threadIdx.x; j < ncol; j += 256) s += X[(int64_t)r * ncol + j];
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
+    const float v = X[(int64_t)r * ncol + j];
+    s = Y ? fmaf(Y[j], v, s) : s + v;
+  }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[r] = red[0];
+  if (threadIdx.x == 0) part[r * RSPLIT + sl] = red[0];
+}
+
+__global__ void rowsum_final_kernel(const float* part, float* out, int rows) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  float s = 0.f;
+  for (int k = 0; k < RSPLIT; ++k) s += part[r * RSPLIT + k];
+  out[r] = s;
 }
 
 // out[o] = sum_b X[b][o]
@@ -306,21 +323,6 @@ __global__ void local_head_kernel(const float* a, const float* Wl, float* z, int
   float s = 0.f;
   for (int c = 0; c < CH; ++c) s = fmaf(Wl[c], a[(int64_t)c * BL + i], s);
   z[i] += s;
-}
-
-// dWl[c] = sum_i dz[i] * a[c][i] (one block per channel, fixed reduction order)
-__global__ void local_head_wgrad_kernel(const float* a, const float* dz, float* g, int64_t BL) {
-  __shared__ float red[256];
-  const int c = blockIdx.x;
-  float s = 0.f;
-  for (int64_t i = threadIdx.x; i < BL; i += 256) s = fmaf(dz[i], a[(int64_t)c * BL + i], s);
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) g[c] = red[0];
 }
 
 // da[c][i] += Wl[c] * dz[i]
@@ -465,45 +467,41 @@ __device__ inline unsigned long long mag_key(float2 v) {
 
 // sigma[(tab * T + t) * nc + c] = median of |R_tab[t][a]| over the fine bins a
 // of coarse bins c-1, c, c+1 (circular) / sqrt(2 ln 2), the local Rayleigh
-// scale of noise-only cells.  The window (3 * per <= LABEL_WIN keys) is sorted
-// in LDS by a bitonic network padded with the largest key; an even count takes
-// the mean of the two middle magnitudes.
-__global__ __launch_bounds__(256) void local_sigma_kernel(const float2* R, const float2* Rc, int T, int nc, int per,
-                                                          double* sigma) {
+// scale of noise-only cells.  The window's W = 3 * per <= LABEL_WIN magnitude
+// keys sit in LDS; the key at sorted position p is the largest key that has
+// at most p keys strictly below it, so each thread counts the keys below its
+// own and offers it to an LDS maximum for the two middle positions (W-1)/2
+// and W/2; an even count takes their mean.  A NULL table is skipped.  The
+// block holds one thread per key, rounded up to whole waves.
+__global__ __launch_bounds__(LABEL_WIN) void local_sigma_kernel(const float2* R, const float2* Rc, int T, int nc,
+                                                                int per, double* sigma) {
   __shared__ unsigned long long key[LABEL_WIN];
+  __shared__ unsigned long long mid[2];
   const int c = blockIdx.x, t = blockIdx.y, tab = blockIdx.z, tid = threadIdx.x;
+  const float2* base = tab ? Rc : R;
+  if (base == nullptr) return;
   const int W = 3 * per;
-  int P = 1;
-  while (P < W) P <<= 1;
-  const float2* row = (tab ? Rc : R) + (int64_t)t * nc * per;
-  for (int i = tid; i < P; i += 256) {
-    unsigned long long k = ~0ull;
-    if (i < W) {
-      int cc = c + i / per - 1;
-      cc = cc < 0 ? cc + nc : (cc >= nc ? cc - nc : cc);
-      k = mag_key(row[(int64_t)cc * per + i % per]);
-    }
-    key[i] = k;
+  const float2* row = base + (int64_t)t * nc * per;
+  if (tid < 2) mid[tid] = 0ull;  // keys are bit patterns of non-negative doubles
+  for (int i = tid; i < W; i += blockDim.x) {
+    int cc = c + i / per - 1;
+    cc = cc < 0 ? cc + nc : (cc >= nc ? cc - nc : cc);
+    key[i] = mag_key(row[(int64_t)cc * per + i % per]);
   }
   __syncthreads();
-  for (int size = 2; size <= P; size <<= 1)
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = tid; i < P; i += 256) {
-        const int j = i ^ stride;
-        if (j > i) {
-          const unsigned long long u = key[i], v = key[j];
-          if ((u > v) == ((i & size) == 0)) {
-            key[i] = v;
-            key[j] = u;
-          }
-        }
-      }
-      __syncthreads();
-    }
+  const int lo = (W - 1) / 2, hi = W / 2;
+  for (int i = tid; i < W; i += blockDim.x) {
+    const unsigned long long k = key[i];
+    int below = 0;
+    for (int j = 0; j < W; ++j) below += key[j] < k ? 1 : 0;
+    if (below <= lo) atomicMax(&mid[0], k);
+    if (below <= hi) atomicMax(&mid[1], k);
+  }
+  __syncthreads();
   if (tid == 0) {
-    const double lo = __longlong_as_double((long long)key[(W - 1) / 2]);
-    const double hi = __longlong_as_double((long long)key[W / 2]);
-    sigma[((int64_t)tab * T + t) * nc + c] = ((W & 1) ? lo : (lo + hi) / 2.0) / 1.1774100225154747;
+    const double l = __longlong_as_double((long long)mid[0]);
+    const double h = __longlong_as_double((long long)mid[1]);
+    sigma[((int64_t)tab * T + t) * nc + c] = ((W & 1) ? l : (l + h) / 2.0) / 1.1774100225154747;
   }
 }
 
@@ -517,6 +515,7 @@ __global__ void coarse_label_kernel(const float2* R, const float2* Rc, int T, in
   for (int tab = 0; tab < 2; ++tab) {
     if (tab == 0 && c == zero_bin) continue;
     const float2* Rt = tab ? Rc : R;
+    if (Rt == nullptr) continue;
     for (int e = threadIdx.x; e < T * per; e += blockDim.x) {
       const int t = e / per, f = e % per;
       const float2 v = Rt[(int64_t)t * A + (int64_t)c * per + f];
@@ -650,6 +649,7 @@ struct cyc_model {
   double* partial = nullptr;
   float2* tw = nullptr;
   float* ws = nullptr;  // split-K partial products
+  float* rpart = nullptr;  // row-sum partials [CH][RSPLIT]
   int64_t ws_cap = 0;
   float* pfeat = nullptr;    // cyc_propose: features [CIN][B][LEN]
   float* pprob = nullptr;    // cyc_propose: probabilities [B][NOUT]
@@ -670,7 +670,7 @@ int64_t model_nparams() {
 void model_free(cyc_model* m) {
   if (!m) return;
   float* bufs[] = {m->w,  m->g, m->m,  m->v,  m->col, m->dcol,  m->hbuf,
-                   m->z,  m->dz, m->da, m->db2, m->ws, m->pfeat, m->pprob};
+                   m->z,  m->dz, m->da, m->db2, m->ws, m->pfeat, m->pprob, m->rpart};
   for (float* p : bufs) (void)hipFree(p);
   for (int i = 0; i < NCONV; ++i) {
     (void)hipFree(m->u[i]);
@@ -730,8 +730,9 @@ hipError_t model_backward(cyc_model* m, const float* feat, const float* labels, 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(head_layout_kernel, dim3(nb((int64_t)n * HDIM)), dim3(256), 0, st, m->hbuf, m->da, n, 1);
   const int64_t BL = (int64_t)n * LEN;
-  hipLaunchKernelGGL(local_head_wgrad_kernel, dim3(CH), dim3(256), 0, st, m->a[NCONV - 1], m->dz, m->g + m->offWl,
-                     BL);
+  // dWl[c] = sum_i dz[i] a[c][i]
+  hipLaunchKernelGGL(rowsum_part_kernel, dim3(CH, RSPLIT), dim3(256), 0, st, m->a[NCONV - 1], m->dz, m->rpart, BL);
+  hipLaunchKernelGGL(rowsum_final_kernel, dim3(1), dim3(CH), 0, st, m->rpart, m->g + m->offWl, CH);
   hipLaunchKernelGGL(local_head_dgrad_kernel, dim3(nb((int64_t)CH * BL)), dim3(256), 0, st, m->da,
                      m->w + m->offWl, m->dz, BL);
   for (int i = NCONV - 1; i >= 0; --i) {
@@ -743,7 +744,9 @@ hipError_t model_backward(cyc_model* m, const float* feat, const float* labels, 
     e = gemm(m->prec, false, true, m->da, m->col, m->g + m->offW[i], CH, cin * KW, (int)BL, (int)BL, (int)BL,
              cin * KW, false, st, m->ws, m->ws_cap);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(rowsum_kernel, dim3(CH), dim3(256), 0, st, m->da, m->g + m->offb[i], BL);
+    hipLaunchKernelGGL(rowsum_part_kernel, dim3(CH, RSPLIT), dim3(256), 0, st, m->da, (const float*)nullptr,
+                       m->rpart, BL);
+    hipLaunchKernelGGL(rowsum_final_kernel, dim3(1), dim3(CH), 0, st, m->rpart, m->g + m->offb[i], CH);
     if (i > 0) {
       e = gemm(m->prec, true, false, m->w + m->offW[i], m->da, m->dcol, cin * KW, (int)BL, CH, cin * KW,
                (int)BL, (int)BL, false, st, m->ws, m->ws_cap);
@@ -806,7 +809,7 @@ int cyc_model_create(cyc_model** out, int32_t max_batch, uint32_t flags, void* s
   m->ws_cap = (int64_t)1 << 24;
   ok = ok && dal(&m->ws, m->ws_cap) == hipSuccess && dal(&m->pfeat, (int64_t)CIN * BL) == hipSuccess &&
        dal(&m->pprob, (int64_t)max_batch * NOUT) == hipSuccess &&
-       dal(&m->psel, (int64_t)max_batch * NOUT) == hipSuccess;
+       dal(&m->psel, (int64_t)max_batch * NOUT) == hipSuccess && dal(&m->rpart, (int64_t)CH * RSPLIT) == hipSuccess;
   for (int i = 0; i < NCONV && ok; ++i)
     ok = dal(&m->u[i], (int64_t)CH * BL) == hipSuccess && dal(&m->a[i], (int64_t)CH * BL) == hipSuccess;
   if (!ok) {
@@ -927,7 +930,7 @@ int cyc_propose(cyc_model* m, const void* d_x, int32_t n_windows, int32_t topk, 
 
 int cyc_peak_labels(const void* d_R, const void* d_Rc, int32_t n_lag, int32_t n_alpha, int32_t n_coarse,
                     int32_t zero_bin, float thresh, float* d_labels, void* stream) {
-  if (!d_R || !d_Rc || !d_labels || n_lag < 1 || n_lag > 65535 || n_alpha < 1 || n_coarse < 1 ||
+  if ((!d_R && !d_Rc) || !d_labels || n_lag < 1 || n_lag > 65535 || n_alpha < 1 || n_coarse < 1 ||
       n_alpha % n_coarse != 0 || 3 * (n_alpha / n_coarse) > LABEL_WIN || zero_bin < -1 || zero_bin >= n_coarse ||
       !(thresh > 0.f))
     return CYC_EINVAL;
@@ -937,7 +940,8 @@ int cyc_peak_labels(const void* d_R, const void* d_Rc, int32_t n_lag, int32_t n_
   if (hipMallocAsync(reinterpret_cast<void**>(&sigma), sizeof(double) * 2 * n_lag * (size_t)n_coarse, st) !=
       hipSuccess)
     return CYC_ENOMEM;
-  hipLaunchKernelGGL(local_sigma_kernel, dim3(n_coarse, n_lag, 2), dim3(256), 0, st,
+  const int sig_threads = (3 * per + 63) / 64 * 64;
+  hipLaunchKernelGGL(local_sigma_kernel, dim3(n_coarse, n_lag, 2), dim3(sig_threads), 0, st,
                      reinterpret_cast<const float2*>(d_R), reinterpret_cast<const float2*>(d_Rc), n_lag, n_coarse,
                      per, sigma);
   hipLaunchKernelGGL(coarse_label_kernel, dim3(n_coarse), dim3(256), 0, st, reinterpret_cast<const float2*>(d_R),

@@ -631,9 +631,10 @@ def cyc_select(prob, topk: int = 16, width: int = 2, zero_bin: int = N_COARSE //
 
 def cyc_peak_labels(R, Rc, n_coarse: int = N_COARSE, zero_bin: int = N_COARSE // 2, thresh: float = 7.0,
                     stream=None):
-    """R, Rc: complex64 CUDA tensors [T, A] -> float labels [n_coarse] on the GPU."""
+    """R, Rc: complex64 CUDA tensors [T, A] (either may be None) -> float labels [n_coarse] on the GPU."""
     import torch
-    lab = torch.empty(n_coarse, dtype=torch.float32, device=R.device)
-    _check(lib().cyc_peak_labels(_p(R), _p(Rc), R.shape[0], R.shape[1], int(n_coarse), int(zero_bin),
+    ref = R if R is not None else Rc
+    lab = torch.empty(n_coarse, dtype=torch.float32, device=ref.device)
+    _check(lib().cyc_peak_labels(_p(R), _p(Rc), ref.shape[0], ref.shape[1], int(n_coarse), int(zero_bin),
                                  float(thresh), _p(lab), _stream_handle(stream)), "cyc_peak_labels")
     return lab

@@ -94,7 +94,6 @@ class FullGrid:
             raise ValueError(mode)
         self.R = torch.empty((T_LAG, FINE), dtype=torch.complex64, device="cuda")
         self.Rc = torch.empty_like(self.R)
-        self.zero = torch.zeros_like(self.R)
 
     def tables(self, x):
         self.st.reset()
@@ -112,15 +111,15 @@ class FullGrid:
 def label_windows(xd, fg: FullGrid, thresh: float = 7.0):
     """Labels of device windows xd [n, 65536]: (non-conjugate, conjugate), each [n, 1024] on the GPU.
 
-    The label of a coarse bin is the larger of the two (a table of zeros has no peaks).
+    Each label call is given one table; the other is NULL and contributes no peaks.
     """
     import torch
     acf = torch.empty((xd.shape[0], N_COARSE), dtype=torch.float32, device="cuda")
     conj = torch.empty_like(acf)
     for i in range(xd.shape[0]):
         R, Rc = fg.tables(xd[i])
-        acf[i] = cyclo.cyc_peak_labels(R, fg.zero, N_COARSE, ZERO_BIN, thresh)
-        conj[i] = cyclo.cyc_peak_labels(fg.zero, Rc, N_COARSE, ZERO_BIN, thresh)
+        acf[i] = cyclo.cyc_peak_labels(R, None, N_COARSE, ZERO_BIN, thresh)
+        conj[i] = cyclo.cyc_peak_labels(None, Rc, N_COARSE, ZERO_BIN, thresh)
     return acf, conj
 
 

@@ -180,6 +180,26 @@ def test_label_noise_scale_matches_oracle_median(cy):
     assert np.array_equal(lab, ref.astype(np.float32))
 
 
+def test_labels_with_one_table(cy):
+    # a NULL table contributes no peaks: one-table labels equal the oracle's with
+    # a zero table, and their union the two-table labels
+    T, A, n_coarse = 6, 4096, 64
+    x = siggen.mixed_stream(6, 4, n=20000)[0]
+    alphas = -0.5 + np.arange(A) / A
+    R, Rc, _ = cyclic_tables(x, alphas, T)
+    R32, Rc32 = R.astype(np.complex64), Rc.astype(np.complex64)
+    z = np.zeros_like(R)
+    want_a = P.coarse_labels(R32.astype(np.complex128), z, n_coarse, zero_bin=32)
+    want_c = P.coarse_labels(z, Rc32.astype(np.complex128), n_coarse, zero_bin=32)
+    dR, dRc = torch.from_numpy(R32).to("cuda"), torch.from_numpy(Rc32).to("cuda")
+    la = cy.cyc_peak_labels(dR, None, n_coarse=n_coarse, zero_bin=32).cpu().numpy()
+    lc = cy.cyc_peak_labels(None, dRc, n_coarse=n_coarse, zero_bin=32).cpu().numpy()
+    both = cy.cyc_peak_labels(dR, dRc, n_coarse=n_coarse, zero_bin=32).cpu().numpy()
+    assert want_a.sum() > 0 and want_c.sum() > 0
+    assert np.array_equal(la, want_a.astype(np.float32)) and np.array_equal(lc, want_c.astype(np.float32))
+    assert np.array_equal(both, np.maximum(la, lc))
+
+
 def test_propose_equals_its_steps_and_the_oracle_selection(cy):
     # cyc_propose (spectra -> network -> selection -> compaction) against the
     # separate calls on the same windows, and its bins against the oracle's
