@@ -328,7 +328,9 @@ __device__ __forceinline__ void contract_f32_tile(const ContractArgs& a, TileId 
       const int buf = ks & 1;
       const int xb2 = xb == 0 ? 2 : xb - 1;  // (ks + 2) % 3
       stg.load(a.v, a.vy, tl.cbase + (int64_t)(ks + 2) * KS, tl.tau0, tl.yend, hptr(ks + 2), tid);
+      __builtin_amdgcn_s_setprio(1);  // as in the 16-bit kernel
       mfma_step(xb, buf);
+      __builtin_amdgcn_s_setprio(0);
       produce(buf ^ 1, hnext);
       stg.store(&Xh[xb2][0], &Xy[buf][0], tid);
       hnext = stg.hv;
@@ -500,7 +502,11 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
     for (int ks = 0; ks + 1 < ns; ++ks) {
       const int buf = ks & 1;
       stg.load(a.v, a.vy, tl.cbase + (int64_t)(ks + 2) * KS, tl.tau0, tl.yend, hptr(ks + 2), tid);
+      // The wave issuing matrix-core work runs at raised priority; the other
+      // resident wave's operand generation fills the issue slots it leaves.
+      __builtin_amdgcn_s_setprio(1);
       mfma_step(buf);
+      __builtin_amdgcn_s_setprio(0);
       produce(buf ^ 1, hnext);
       stg.store(&Xh[buf][0], &Xy[buf][0], tid);
       hnext = stg.hv;
