@@ -240,9 +240,23 @@ def dataset(model, fg: FullGrid, seed: int, first: int, n: int, keep_windows: bo
     """Features [3, n, 1024] and labels [n, 1024] (GPU) of n windows, made chunk by chunk."""
     import torch
     feats, acfs, conjs, wins = [], [], [], []
-    for s in range(0, n, chunk):
+    starts = list(range(0, n, chunk))
+
+    def submit(s):  # the pool makes the next chunk's windows while this one is labelled
         m = min(chunk, n - s)
-        xd = torch.from_numpy(make_windows(seed, first + s, m, pool)).to("cuda")
+        args = [(seed, first + s + i) for i in range(m)]
+        return pool.map_async(_window, args, chunksize=16) if pool is not None else None
+
+    pending = submit(starts[0]) if starts else None
+    for k, s in enumerate(starts):
+        m = min(chunk, n - s)
+        if pool is not None:
+            xs = np.stack(pending.get())
+            if k + 1 < len(starts):
+                pending = submit(starts[k + 1])
+        else:
+            xs = make_windows(seed, first + s, m)
+        xd = torch.from_numpy(xs).to("cuda")
         a, c = label_windows(xd, fg)
         acfs.append(a)
         conjs.append(c)
