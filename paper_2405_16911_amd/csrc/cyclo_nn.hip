@@ -467,41 +467,88 @@ __device__ inline unsigned long long mag_key(float2 v) {
 
 // sigma[(tab * T + t) * nc + c] = median of |R_tab[t][a]| over the fine bins a
 // of coarse bins c-1, c, c+1 (circular) / sqrt(2 ln 2), the local Rayleigh
-// scale of noise-only cells.  The window's W = 3 * per <= LABEL_WIN magnitude
-// keys sit in LDS; the key at sorted position p is the largest key that has
-// at most p keys strictly below it, so each thread counts the keys below its
-// own and offers it to an LDS maximum for the two middle positions (W-1)/2
-// and W/2; an even count takes their mean.  A NULL table is skipped.  The
-// block holds one thread per key, rounded up to whole waves.
-__global__ __launch_bounds__(LABEL_WIN) void local_sigma_kernel(const float2* R, const float2* Rc, int T, int nc,
-                                                                int per, double* sigma) {
-  __shared__ unsigned long long key[LABEL_WIN];
-  __shared__ unsigned long long mid[2];
-  const int c = blockIdx.x, t = blockIdx.y, tab = blockIdx.z, tid = threadIdx.x;
+// scale of noise-only cells.  A workgroup takes one (table, lag) and a run of
+// cb windows: it loads the magnitude keys of coarse bins c0-1 .. c0+cb into
+// LDS, one segment of P2 >= per slots per bin (padded with the largest key),
+// and sorts every segment at once with a bitonic network.  The key at sorted
+// position p of a window is the largest key with at most p keys of the window
+// strictly below it; that count is three binary searches, one per sorted
+// segment, and an LDS maximum keeps the keys for the two middle positions
+// (W-1)/2 and W/2 of W = 3 per.  An even count takes their mean.  A NULL table
+// is skipped.
+constexpr int SIG_SLOTS = 2048;  // LDS key slots per workgroup: (cb + 2) * P2
+
+__host__ __device__ inline int sig_p2(int per) {
+  int p2 = 1;
+  while (p2 < per) p2 <<= 1;
+  return p2;
+}
+__host__ __device__ inline int sig_cb(int per, int nc) {
+  const int cb = SIG_SLOTS / sig_p2(per) - 2;
+  const int lim = nc < SIG_SLOTS / 2 ? nc : SIG_SLOTS / 2;  // windows per workgroup <= the maxima kept
+  return cb < 1 ? 1 : (cb > lim ? lim : cb);
+}
+
+__global__ __launch_bounds__(256) void local_sigma_kernel(const float2* R, const float2* Rc, int T, int nc,
+                                                          int per, double* sigma) {
+  __shared__ unsigned long long key[SIG_SLOTS];
+  __shared__ unsigned long long mid[SIG_SLOTS / 2][2];
+  const int t = blockIdx.y, tab = blockIdx.z, tid = threadIdx.x;
   const float2* base = tab ? Rc : R;
   if (base == nullptr) return;
-  const int W = 3 * per;
+  const int p2 = sig_p2(per), cb = sig_cb(per, nc);
+  const int c0 = blockIdx.x * cb;
+  const int nw = min(cb, nc - c0);  // windows of this workgroup
+  const int nseg = nw + 2, nkeys = nseg * p2;
   const float2* row = base + (int64_t)t * nc * per;
-  if (tid < 2) mid[tid] = 0ull;  // keys are bit patterns of non-negative doubles
-  for (int i = tid; i < W; i += blockDim.x) {
-    int cc = c + i / per - 1;
+  for (int i = tid; i < nkeys; i += 256) {
+    const int sg = i / p2, j = i % p2;
+    int cc = c0 - 1 + sg;
     cc = cc < 0 ? cc + nc : (cc >= nc ? cc - nc : cc);
-    key[i] = mag_key(row[(int64_t)cc * per + i % per]);
+    key[i] = j < per ? mag_key(row[(int64_t)cc * per + j]) : ~0ull;
   }
+  for (int i = tid; i < nw; i += 256) mid[i][0] = mid[i][1] = 0ull;  // keys are >= 0
   __syncthreads();
-  const int lo = (W - 1) / 2, hi = W / 2;
-  for (int i = tid; i < W; i += blockDim.x) {
-    const unsigned long long k = key[i];
+  // bitonic sort of every segment (ascending)
+  for (int k = 2; k <= p2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < nkeys; i += 256) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool up = ((i % p2) & k) == 0;
+          const unsigned long long a = key[i], b = key[l];
+          if ((a > b) == up) {
+            key[i] = b;
+            key[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const int W = 3 * per, lo = (W - 1) / 2, hi = W / 2;
+  for (int q = tid; q < nw * W; q += 256) {
+    const int w = q / W, e = q % W;
+    const unsigned long long k = key[(w + e / per) * p2 + e % per];
+    // three independent searches, stepped together; after them keys
+    // sgk[d][0 .. pos[d]) are below k
+    const unsigned long long* sgk = key + w * p2;
+    int pos[3] = {0, p2, 2 * p2};
+    for (int st = p2 >> 1; st > 0; st >>= 1) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) pos[d] += sgk[pos[d] + st - 1] < k ? st : 0;
+    }
     int below = 0;
-    for (int j = 0; j < W; ++j) below += key[j] < k ? 1 : 0;
-    if (below <= lo) atomicMax(&mid[0], k);
-    if (below <= hi) atomicMax(&mid[1], k);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) below += pos[d] - d * p2 + (sgk[pos[d]] < k ? 1 : 0);
+    if (below <= lo) atomicMax(&mid[w][0], k);
+    if (below <= hi) atomicMax(&mid[w][1], k);
   }
   __syncthreads();
-  if (tid == 0) {
-    const double l = __longlong_as_double((long long)mid[0]);
-    const double h = __longlong_as_double((long long)mid[1]);
-    sigma[((int64_t)tab * T + t) * nc + c] = ((W & 1) ? l : (l + h) / 2.0) / 1.1774100225154747;
+  for (int w = tid; w < nw; w += 256) {
+    const double l = __longlong_as_double((long long)mid[w][0]);
+    const double h = __longlong_as_double((long long)mid[w][1]);
+    sigma[((int64_t)tab * T + t) * nc + c0 + w] = ((W & 1) ? l : (l + h) / 2.0) / 1.1774100225154747;
   }
 }
 
@@ -940,8 +987,8 @@ int cyc_peak_labels(const void* d_R, const void* d_Rc, int32_t n_lag, int32_t n_
   if (hipMallocAsync(reinterpret_cast<void**>(&sigma), sizeof(double) * 2 * n_lag * (size_t)n_coarse, st) !=
       hipSuccess)
     return CYC_ENOMEM;
-  const int sig_threads = (3 * per + 63) / 64 * 64;
-  hipLaunchKernelGGL(local_sigma_kernel, dim3(n_coarse, n_lag, 2), dim3(sig_threads), 0, st,
+  const int sig_cbins = sig_cb(per, n_coarse);
+  hipLaunchKernelGGL(local_sigma_kernel, dim3((n_coarse + sig_cbins - 1) / sig_cbins, n_lag, 2), dim3(256), 0, st,
                      reinterpret_cast<const float2*>(d_R), reinterpret_cast<const float2*>(d_Rc), n_lag, n_coarse,
                      per, sigma);
   hipLaunchKernelGGL(coarse_label_kernel, dim3(n_coarse), dim3(256), 0, st, reinterpret_cast<const float2*>(d_R),

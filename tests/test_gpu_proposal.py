@@ -160,6 +160,31 @@ def test_labels_match_oracle(cy, A, n_coarse, zero_bin):
     assert np.array_equal(lab, ref.astype(np.float32))
 
 
+@pytest.mark.parametrize("A,n_coarse,thresh", [(1023, 3, 4.0), (50, 50, 3.0), (96, 4, 3.0), (6400, 100, 3.0),
+                                               (8192, 1024, 3.0)])
+def test_labels_random_tables_match_oracle(cy, A, n_coarse, thresh):
+    # Rayleigh-like tables whose scale changes from coarse bin to coarse bin,
+    # rounded to quarter steps so that many magnitudes tie; 341, 1, 24, 64 and
+    # 8 fine bins per coarse bin (one or several workgroups, a partial last one,
+    # windows that wrap around the circle)
+    rng = np.random.default_rng(A + n_coarse)
+    T = 3
+    scale = np.repeat(rng.uniform(0.5, 2.0, size=n_coarse), A // n_coarse)[None, :]
+
+    def table():
+        z = (rng.standard_normal((T, A)) + 1j * rng.standard_normal((T, A))) * scale
+        return (np.round(z * 4) / 4).astype(np.complex64)
+
+    R, Rc = table(), table()
+    zb = n_coarse // 2
+    ref = P.coarse_labels(R.astype(np.complex128), Rc.astype(np.complex128), n_coarse, zero_bin=zb, thresh=thresh)
+    lab = cy.cyc_peak_labels(torch.from_numpy(R).to("cuda"), torch.from_numpy(Rc).to("cuda"),
+                             n_coarse=n_coarse, zero_bin=zb, thresh=thresh).cpu().numpy()
+    print(f"  A={A} n_coarse={n_coarse}: {int(ref.sum())} positive", flush=True)
+    assert 0 < ref.sum() < n_coarse
+    assert np.array_equal(lab, ref.astype(np.float32))
+
+
 def test_label_noise_scale_matches_oracle_median(cy):
     # 8 coarse bins of 8: each window holds 24 magnitudes, the median is the mean
     # of the 12th and 13th.  Both rows put 12 values of 0.25 and 12 larger ones
