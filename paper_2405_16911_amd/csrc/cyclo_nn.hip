@@ -43,21 +43,27 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
 // ----------------------------------------------------------------------------- GEMM
 //
 // C[M][N] (row-major, ldc) (+)= op(A) . op(B), op(A)[m][k] = TA ? A[k*lda+m] : A[m*lda+k],
-// op(B)[k][n] = TB ? B[n*ldb+k] : B[k*ldb+n].  128x128 tiles, 32-deep K steps,
-// four waves of 64x64 (2x2 blocks of 32x32 MFMA).  Tiles are staged in LDS
-// k-contiguous (FP32) and rounded to BF16 while forming fragments in BF16 mode.
-// Split K: block z covers k in [z*kchunk, (z+1)*kchunk) and, when part is set,
-// writes its partial product to part[z][M][N] for splitk_reduce_kernel.
-template <int PREC, int TA, int TB>
+// op(B)[k][n] = TB ? B[n*ldb+k] : B[k*ldb+n].  Four waves of 64x64 (2x2 blocks
+// of 32x32 MFMA) tile BM x BN = 128 x 128 (WMW = 2) or 64 x 256 (WMW = 1, for
+// M <= 64), in 32-deep K steps.  Tiles are staged in LDS k-contiguous: in BF16
+// mode as packed pairs, each value rounded to BF16 once while it is staged; in
+// FP32 mode as floats.  The LDS tiles are double-buffered and the next step's
+// global loads are issued before this step's matrix-core work, one barrier per
+// step.  Split K: block z covers k in [z*kchunk, (z+1)*kchunk) and, when part
+// is set, writes its partial product to part[z][M][N] for splitk_reduce_kernel.
+template <int PREC, int TA, int TB, int WMW>
 __global__ __launch_bounds__(256) void gemm_kernel(const float* __restrict__ A,
                                                    const float* __restrict__ B, float* __restrict__ C,
                                                    int M, int N, int K, int lda, int ldb, int ldc,
                                                    int accumulate, int kchunk, float* __restrict__ part) {
-  constexpr int BM = 128, BN = 128, BK = 32, LP = BK + 4;
-  __shared__ __attribute__((aligned(16))) float As[BM][LP];
-  __shared__ __attribute__((aligned(16))) float Bs[BN][LP];
+  constexpr int BM = 64 * WMW, BN = 64 * (4 / WMW), BK = 32;
+  constexpr int KW = PREC ? BK / 2 : BK;  // LDS words per tile row: BF16 pairs or floats
+  constexpr int LP = KW + 4;              // row pitch in words, rows 16-byte aligned
+  constexpr int NA = BM * KW / 256, NB = BN * KW / 256;  // words each thread stages
+  __shared__ __attribute__((aligned(16))) uint32_t As[2][BM][LP];
+  __shared__ __attribute__((aligned(16))) uint32_t Bs[2][BN][LP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1, h = lane >> 5, l32 = lane & 31;
+  const int wm = wave % WMW, wn = wave / WMW, h = lane >> 5, l32 = lane & 31;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   f32x16 acc[2][2];
 #pragma unroll
@@ -68,56 +74,58 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float* __restrict__ A,
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
   const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    // A tile -> As[m][k]
+  // Element (row r, k) of op(X) with bounds check; the load is unconditional
+  // (from element 0 when out of range) and the value is masked afterwards.
+  auto ld = [](const float* X, int ldx, bool trans, int r, int nr, int k, int kend_) {
+    const bool ok = r < nr && k < kend_;
+    const float v = X[ok ? (trans ? (int64_t)k * ldx + r : (int64_t)r * ldx + k) : 0];
+    return ok ? v : 0.f;
+  };
+  // word w of tile row r holds k = k0 + 2w, k0 + 2w + 1 (BF16) or k = k0 + w (FP32);
+  // thread e stages word (e % KW) of row (e / KW), or, when the rows are
+  // contiguous in memory (a transposed operand), word (e / rows) of row (e % rows)
+  uint32_t ra[NA], rb[NB];
+  auto fetch = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      int mm, kk;
-      if (TA) {  // m contiguous in memory
-        const int e = tid + i * 256;
-        kk = e / BM;
-        mm = e % BM;
-      } else {
-        const int e = tid + i * 256;
-        mm = e / BK;
-        kk = e % BK;
-      }
-      const int gm = m0 + mm, gk = k0 + kk;
-      float v = 0.f;
-      if (gm < M && gk < kend) v = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
-      As[mm][kk] = v;
+    for (int i = 0; i < NA; ++i) {
+      const int e = tid + i * 256;
+      const int r = TA ? e % BM : e / KW, w = TA ? e / BM : e % KW;
+      if (PREC)
+        ra[i] = pack_bf16(ld(A, lda, TA, m0 + r, M, k0 + 2 * w, kend), ld(A, lda, TA, m0 + r, M, k0 + 2 * w + 1, kend));
+      else
+        ra[i] = __float_as_uint(ld(A, lda, TA, m0 + r, M, k0 + w, kend));
     }
-    // B tile -> Bs[n][k]
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      int nn, kk;
-      if (TB) {  // k contiguous in memory
-        const int e = tid + i * 256;
-        nn = e / BK;
-        kk = e % BK;
-      } else {
-        const int e = tid + i * 256;
-        kk = e / BN;
-        nn = e % BN;
-      }
-      const int gn = n0 + nn, gk = k0 + kk;
-      float v = 0.f;
-      if (gn < N && gk < kend) v = TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
-      Bs[nn][kk] = v;
+    for (int i = 0; i < NB; ++i) {
+      const int e = tid + i * 256;
+      const int r = TB ? e / KW : e % BN, w = TB ? e % KW : e / BN;
+      if (PREC)
+        rb[i] = pack_bf16(ld(B, ldb, !TB, n0 + r, N, k0 + 2 * w, kend), ld(B, ldb, !TB, n0 + r, N, k0 + 2 * w + 1, kend));
+      else
+        rb[i] = __float_as_uint(ld(B, ldb, !TB, n0 + r, N, k0 + w, kend));
     }
-    __syncthreads();
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = tid + i * 256;
+      As[buf][TA ? e % BM : e / KW][TA ? e / BM : e % KW] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int e = tid + i * 256;
+      Bs[buf][TB ? e / KW : e % BN][TB ? e % KW : e / BN] = rb[i];
+    }
+  };
+  auto compute = [&](int buf) {
     if (PREC == 1) {
 #pragma unroll
       for (int kb = 0; kb < BK / 16; ++kb) {
         uint4 af[2], bf[2];
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
-          const float* ap = &As[wm * 64 + r * 32 + l32][kb * 16 + 8 * h];
-          const float* bp = &Bs[wn * 64 + r * 32 + l32][kb * 16 + 8 * h];
-          af[r] = make_uint4(pack_bf16(ap[0], ap[1]), pack_bf16(ap[2], ap[3]), pack_bf16(ap[4], ap[5]),
-                             pack_bf16(ap[6], ap[7]));
-          bf[r] = make_uint4(pack_bf16(bp[0], bp[1]), pack_bf16(bp[2], bp[3]), pack_bf16(bp[4], bp[5]),
-                             pack_bf16(bp[6], bp[7]));
+          af[r] = *reinterpret_cast<const uint4*>(&As[buf][wm * 64 + r * 32 + l32][kb * 8 + 4 * h]);
+          bf[r] = *reinterpret_cast<const uint4*>(&Bs[buf][wn * 64 + r * 32 + l32][kb * 8 + 4 * h]);
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -132,8 +140,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float* __restrict__ A,
         float af[2], bf[2];
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
-          af[r] = As[wm * 64 + r * 32 + l32][k + h];
-          bf[r] = Bs[wn * 64 + r * 32 + l32][k + h];
+          af[r] = __uint_as_float(As[buf][wm * 64 + r * 32 + l32][k + h]);
+          bf[r] = __uint_as_float(Bs[buf][wn * 64 + r * 32 + l32][k + h]);
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -142,7 +150,21 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float* __restrict__ A,
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bf[j], acc[i][j], 0, 0, 0);
       }
     }
+  };
+
+  if (kbeg < kend) {
+    fetch(kbeg);
+    stash(0);
     __syncthreads();
+    int buf = 0;
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+      const bool more = k0 + BK < kend;
+      if (more) fetch(k0 + BK);
+      compute(buf);
+      if (more) stash(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -182,7 +204,9 @@ __global__ void splitk_reduce_kernel(const float* __restrict__ part, float* __re
 hipError_t gemm(int prec, bool ta, bool tb, const float* A, const float* B, float* C, int M, int N, int K,
                 int lda, int ldb, int ldc, bool accumulate, hipStream_t st, float* ws = nullptr,
                 int64_t ws_cap = 0) {
-  const int tiles = ((N + 127) / 128) * ((M + 127) / 128);
+  const int wmw = M <= 64 ? 1 : 2;  // 64 x 256 tiles when one 64-row tile covers M
+  const int BM = 64 * wmw, BN = 64 * (4 / wmw);
+  const int tiles = ((N + BN - 1) / BN) * ((M + BM - 1) / BM);
   int S = 1;
   if (ws && tiles < 512) {
     S = std::min((512 + tiles - 1) / tiles, K / 512);
@@ -192,16 +216,19 @@ hipError_t gemm(int prec, bool ta, bool tb, const float* A, const float* B, floa
   const int kchunk = S > 1 ? ((K + S - 1) / S + 31) / 32 * 32 : K;
   if (S > 1) S = (K + kchunk - 1) / kchunk;
   float* part = S > 1 ? ws : nullptr;
-  const dim3 grid((N + 127) / 128, (M + 127) / 128, S);
+  const dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, S);
   bool launched = false;
-#define GEMM_CASE(P, X, Y)                                                                           \
-  if (!launched && prec == P && ta == (bool)X && tb == (bool)Y) {                                    \
-    hipLaunchKernelGGL((gemm_kernel<P, X, Y>), grid, dim3(256), 0, st, A, B, C, M, N, K, lda, ldb, ldc, \
-                       accumulate ? 1 : 0, kchunk, part);                                            \
-    launched = true;                                                                                 \
+#define GEMM_CASE(P, X, Y, W)                                                                            \
+  if (!launched && prec == P && ta == (bool)X && tb == (bool)Y && wmw == W) {                             \
+    hipLaunchKernelGGL((gemm_kernel<P, X, Y, W>), grid, dim3(256), 0, st, A, B, C, M, N, K, lda, ldb, ldc, \
+                       accumulate ? 1 : 0, kchunk, part);                                                 \
+    launched = true;                                                                                      \
   }
-  GEMM_CASE(0, 0, 0) GEMM_CASE(0, 0, 1) GEMM_CASE(0, 1, 0) GEMM_CASE(0, 1, 1)
-  GEMM_CASE(1, 0, 0) GEMM_CASE(1, 0, 1) GEMM_CASE(1, 1, 0) GEMM_CASE(1, 1, 1)
+#define GEMM_CASES(W)                                                                                     \
+  GEMM_CASE(0, 0, 0, W) GEMM_CASE(0, 0, 1, W) GEMM_CASE(0, 1, 0, W) GEMM_CASE(0, 1, 1, W)                 \
+  GEMM_CASE(1, 0, 0, W) GEMM_CASE(1, 0, 1, W) GEMM_CASE(1, 1, 0, W) GEMM_CASE(1, 1, 1, W)
+  GEMM_CASES(1) GEMM_CASES(2)
+#undef GEMM_CASES
 #undef GEMM_CASE
   if (!launched) return hipErrorInvalidValue;
   if (S > 1)
