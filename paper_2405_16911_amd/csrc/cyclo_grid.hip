@@ -129,20 +129,38 @@ __global__ __launch_bounds__(256) void grid_fft_kernel(const double2* src, doubl
                                                         const double2* tw, int T, double scale, int out_mode,
                                                         void* d_R, void* d_Rc) {
   __shared__ double2 buf[FFT_MAX];
-  const int row = blockIdx.x, j = blockIdx.y, tid = threadIdx.x;
+  // Block b: rows come in groups of 8; within a group b = 8 j + (row mod 8), so
+  // the P sub-transforms of a row, which read interleaved elements of the same
+  // lines, are dispatched together and, with workgroups dealt round-robin over
+  // the eight XCDs, share one XCD's L2.
+  const int grp = blockIdx.x / (8 * P), rem = blockIdx.x % (8 * P);
+  const int row = grp * 8 + rem % 8, j = rem / 8, tid = threadIdx.x;
+  if (row >= 2 * T) return;
   const double2* s = src + (int64_t)row * A;
   for (int i = tid; i < M; i += 256) buf[bitrev(i, logM)] = s[(int64_t)P * i + j];
   __syncthreads();
   const int tstride = A / M;  // w_M^m = tw[m * A / M]
+  constexpr int NBF = FFT_MAX / 512;  // butterflies per thread per stage, at most
   for (int h = 1; h < M; h <<= 1) {
     const int step = tstride * (M / (2 * h));
-    for (int b = tid; b < M / 2; b += 256) {
-      const int jj = b & (h - 1);
-      const int i0 = ((b - jj) << 1) + jj, i1 = i0 + h;
-      const double2 w = tw[(int64_t)jj * step];
-      const double2 u = buf[i0], t = cmul(w, buf[i1]);
-      buf[i0] = make_double2(u.x + t.x, u.y + t.y);
-      buf[i1] = make_double2(u.x - t.x, u.y - t.y);
+    // the stage's twiddles first, all loads in flight together (index 0 for
+    // butterflies past M/2, whose values are not used)
+    double2 w[NBF];
+#pragma unroll
+    for (int q = 0; q < NBF; ++q) {
+      const int b = tid + q * 256;
+      w[q] = tw[b < M / 2 ? (int64_t)(b & (h - 1)) * step : 0];
+    }
+#pragma unroll
+    for (int q = 0; q < NBF; ++q) {
+      const int b = tid + q * 256;
+      if (b < M / 2) {
+        const int jj = b & (h - 1);
+        const int i0 = ((b - jj) << 1) + jj, i1 = i0 + h;
+        const double2 u = buf[i0], t = cmul(w[q], buf[i1]);
+        buf[i0] = make_double2(u.x + t.x, u.y + t.y);
+        buf[i1] = make_double2(u.x - t.x, u.y - t.y);
+      }
     }
     __syncthreads();
   }
@@ -164,29 +182,49 @@ __global__ __launch_bounds__(256) void grid_fft_kernel(const double2* src, doubl
   }
 }
 
-// Second stage for A = P M: X[k] = sum_{j<P} Y[j][k mod M] w_A^{j k}, scaled and
-// written to the output tables.
+// Second stage for A = P M (P <= 8): X[k1 + m M] = sum_{j<P} Y[j][k1] w_A^{j k1} w_P^{j m},
+// one thread per (table row, k1) forming all P outputs of k1 from the P
+// twiddled inputs, scaled and written to the output tables.
+constexpr int COMBINE_MAX = 8;
+static_assert(65536 / FFT_MAX <= COMBINE_MAX, "A <= 65536 splits into at most COMBINE_MAX rows");
 __global__ void grid_combine_kernel(const double2* Y, int A, int M, int P, const double2* tw, int T, double scale,
                                     int out_mode, void* d_R, void* d_Rc) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)2 * T * A) return;
-  const int row = (int)(idx / A), k = (int)(idx % A);
+  if (idx >= (int64_t)2 * T * M) return;
+  const int row = (int)(idx / M), k1 = (int)(idx % M);
   const int tab = row / T, t = row % T;
   void* base = tab ? d_Rc : d_R;
   if (!base) return;
   const double2* y = Y + (int64_t)row * P * M;
-  const int k1 = k % M;
-  double2 s = make_double2(0.0, 0.0);
-  for (int j = 0; j < P; ++j) {
-    const double2 v = cmul(tw[(int64_t)j * k % A], y[(int64_t)j * M + k1]);
-    s.x += v.x;
-    s.y += v.y;
+  double2 v[COMBINE_MAX];
+  int e = 0;  // j k1 mod A
+#pragma unroll
+  for (int j = 0; j < COMBINE_MAX; ++j) {
+    if (j < P) {
+      v[j] = cmul(tw[e], y[(int64_t)j * M + k1]);
+      e += k1;
+      e = e >= A ? e - A : e;
+    }
   }
-  const int64_t o = (int64_t)t * A + k;
-  if (out_mode == 2)
-    reinterpret_cast<double2*>(base)[o] = make_double2(s.x * scale, s.y * scale);
-  else
-    reinterpret_cast<float2*>(base)[o] = make_float2((float)(s.x * scale), (float)(s.y * scale));
+  for (int m = 0; m < P; ++m) {
+    double2 s = make_double2(0.0, 0.0);
+    int f = 0;  // j m M mod A
+#pragma unroll
+    for (int j = 0; j < COMBINE_MAX; ++j) {
+      if (j < P) {
+        const double2 u = cmul(tw[f], v[j]);
+        s.x += u.x;
+        s.y += u.y;
+        f += m * M;
+        f = f >= A ? f - A : f;
+      }
+    }
+    const int64_t o = (int64_t)t * A + k1 + (int64_t)m * M;
+    if (out_mode == 2)
+      reinterpret_cast<double2*>(base)[o] = make_double2(s.x * scale, s.y * scale);
+    else
+      reinterpret_cast<float2*>(base)[o] = make_float2((float)(s.x * scale), (float)(s.y * scale));
+  }
 }
 
 __global__ void grid_twiddle_kernel(int A, double2* tw) {
@@ -236,6 +274,7 @@ struct cyc_grid {
   bool two = false;
   int64_t dx = 0, dy = 0, lagabs = 0;
   bool poisoned = false;
+  bool zero_q = false;  // q is cleared on the stream of the next push (after a reset)
 };
 
 namespace {
@@ -332,6 +371,11 @@ VSrc grid_src(const cyc_grid* g, float2* const* bufs, int64_t d, const float2* b
 }
 
 int grid_push_xy(cyc_grid* g, const float2* x, const float2* y, int64_t n, hipStream_t st) {
+  if (g->zero_q) {
+    const int64_t TA2 = 2 * (int64_t)g->T * g->A;
+    hipLaunchKernelGGL(grid_zero_kernel, dim3(nblk(TA2)), dim3(256), 0, st, g->q, TA2);
+    g->zero_q = false;
+  }
   const int64_t L_new = g->L + n;
   const int64_t nu_new = std::max<int64_t>(0, L_new - (g->T - 1) - g->lagabs);
   const int64_t np = nu_new - g->nc;  // products that now have all their samples
@@ -420,19 +464,17 @@ int cyc_grid_read(cyc_grid* g, void* d_R, void* d_Rc, int64_t* n_used, void* str
   int logM = 0;
   while ((1 << logM) < M) ++logM;
   const double scale = 1.0 / (double)nu;
-  hipLaunchKernelGGL(grid_fft_kernel, dim3(2 * g->T, P), dim3(256), 0, st, g->q, g->Y,
+  hipLaunchKernelGGL(grid_fft_kernel, dim3((unsigned)((2 * g->T + 7) / 8 * 8 * P)), dim3(256), 0, st, g->q, g->Y,
                      g->A, M, logM, P, g->tw, g->T, scale, out_mode, d_R, d_Rc);
   if (P > 1)
-    hipLaunchKernelGGL(grid_combine_kernel, dim3(nblk(2 * TA)), dim3(256), 0, st, g->Y, g->A, M, P, g->tw, g->T,
-                       scale, out_mode, d_R, d_Rc);
+    hipLaunchKernelGGL(grid_combine_kernel, dim3(nblk(2 * (int64_t)g->T * M)), dim3(256), 0, st, g->Y, g->A, M, P,
+                       g->tw, g->T, scale, out_mode, d_R, d_Rc);
   return hipGetLastError() == hipSuccess ? CYC_OK : grid_fail(g);
 }
 
 int cyc_grid_reset(cyc_grid* g) {
   if (!g) return CYC_EINVAL;
-  const int64_t TA2 = 2 * (int64_t)g->T * g->A;
-  hipLaunchKernelGGL(grid_zero_kernel, dim3(nblk(TA2)), dim3(256), 0, nullptr, g->q, TA2);
-  if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) return CYC_EDEVICE;
+  g->zero_q = true;  // the fold bins are cleared by the next push, on its stream
   g->L = 0;
   g->nc = 0;
   g->cur = 0;
