@@ -29,6 +29,8 @@ from . import cyclo, siggen
 
 WINDOW = cyclo.WINDOW
 N_COARSE = cyclo.N_COARSE
+VAL_FIRST = 1 << 24   # first index of the validation windows (training windows start at 0)
+TEST_FIRST = 1 << 25  # first index of the test windows
 FINE = 65536
 PER = FINE // N_COARSE
 ZERO_BIN = N_COARSE // 2
@@ -282,9 +284,11 @@ def run(n_train=4096, n_val=512, n_test=512, epochs=30, batch=128, lr=2e-3, wd=0
     model = cyclo.ProposalModel(max(batch, 512), cyclo.CYC_OP_BF16)
     torch.cuda.synchronize()
     t1 = time.time()
+    # held-out windows come from fixed index ranges, so every training size is
+    # validated and tested on the same windows
     f_tr, ls_tr, _ = dataset(model, fg, seed, 0, n_train, log=log, pool=pool)
-    f_va, ls_va, _ = dataset(model, fg, seed, n_train, n_val, log=log, pool=pool)
-    f_te, ls_te, x_te = dataset(model, fg, seed, n_train + n_val, n_test, keep_windows=True, log=log, pool=pool)
+    f_va, ls_va, _ = dataset(model, fg, seed, VAL_FIRST, n_val, log=log, pool=pool)
+    f_te, ls_te, x_te = dataset(model, fg, seed, TEST_FIRST, n_test, keep_windows=True, log=log, pool=pool)
     l_tr, l_va, l_te = (torch.maximum(*ls) for ls in (ls_tr, ls_va, ls_te))
     torch.cuda.synchronize()
     res["labelling_s"] = time.time() - t1
@@ -320,9 +324,9 @@ def run(n_train=4096, n_val=512, n_test=512, epochs=30, batch=128, lr=2e-3, wd=0
     prob = probabilities(model, f_te, 512)
     sel, conf = cyclo.cyc_select(prob.contiguous(), 16, 2, ZERO_BIN)
     thetas = [0.0, 0.5, 0.8, 0.9, 0.95, 0.98, 0.99, 0.995, 0.999, 1.0]
-    curve = theta_curve(conf[:512], sel[:512], l_te[:512], thetas)
+    curve = theta_curve(conf, sel, l_te, thetas)
     fd = FullGrid("dense")
-    res["speed"] = speed(model, x_te[:512], fd, theta, conf_curve=[c[2] for c in curve], fft=fg)
+    res["speed"] = speed(model, x_te, fd, theta, conf_curve=[c[2] for c in curve], fft=fg)
     fd.close()
     res["theta_curve"] = [dict(theta=c[0], miss_rate=c[1], fallback_rate=c[2], predicted_speedup=p)
                           for c, p in zip(curve, res["speed"].pop("predicted_speedup"))]
@@ -336,17 +340,22 @@ def run(n_train=4096, n_val=512, n_test=512, epochs=30, batch=128, lr=2e-3, wd=0
     return res
 
 
-def _contract_selected(xt, sel_h, idx):
-    """Exact estimator on the fine bins of the selected coarse bins of windows idx (one batch)."""
-    import torch
-    if len(idx) == 0:
-        return None
-    lists = [FINE_GRID.reshape(N_COARSE, PER)[np.nonzero(sel_h[i])[0]].reshape(-1) for i in idx]
-    b = cyclo.CyclicBatch(lists, T_LAG, cyclo.CYC_OP_BF16)
-    b.push([xt[i] for i in idx])
-    out = b.read()
-    b.close()
-    return out
+def _contract_selected(xt, sel_h, idx, chunk: int = 512):
+    """Exact estimator on the fine bins of the selected coarse bins of windows idx.
+
+    One batch per chunk of windows; returns the tables of the first chunk.
+    """
+    first = None
+    for s in range(0, len(idx), chunk):
+        part = idx[s:s + chunk]
+        lists = [FINE_GRID.reshape(N_COARSE, PER)[np.nonzero(sel_h[i])[0]].reshape(-1) for i in part]
+        b = cyclo.CyclicBatch(lists, T_LAG, cyclo.CYC_OP_BF16)
+        b.push([xt[i] for i in part])
+        out = b.read()
+        b.close()
+        if first is None:
+            first = out
+    return first
 
 
 def speed(model, xt, fg: FullGrid, theta: float, conf_curve=None, fft: FullGrid = None):
@@ -374,7 +383,7 @@ def speed(model, xt, fg: FullGrid, theta: float, conf_curve=None, fft: FullGrid 
         t_fft = time.perf_counter() - t
     t = time.perf_counter()
     feat = model.spectra(xt.reshape(-1))
-    prob = model.forward(feat)
+    prob = probabilities(model, feat, 512)   # the network takes at most 512 windows per call
     sel, conf = cyclo.cyc_select(prob, 16, 2, ZERO_BIN)
     torch.cuda.synchronize()
     t_front = time.perf_counter() - t
