@@ -82,8 +82,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float* __restrict__ A,
     return ok ? v : 0.f;
   };
   // word w of tile row r holds k = k0 + 2w, k0 + 2w + 1 (BF16) or k = k0 + w (FP32);
-  // thread e stages word (e % KW) of row (e / KW), or, when the rows are
-  // contiguous in memory (a transposed operand), word (e / rows) of row (e % rows)
+  // thread e stages word (e % KW) of row (e / KW), or, when consecutive rows
+  // are adjacent in memory (A with TA, B without TB), word (e / rows) of row
+  // (e % rows), so that neighbouring threads load neighbouring elements
   uint32_t ra[NA], rb[NB];
   auto fetch = [&](int k0) {
 #pragma unroll
