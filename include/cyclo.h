@@ -193,8 +193,10 @@ int cyc_set_kernel_cfg(cyc_state* s, int32_t idx);
 /*
  * Autotuner.  Times every configuration that implements `flags` on pushes of
  * synthetic samples (16 chunks each) into a state of n_alpha cycle
- * frequencies and n_lag lags (HIP events on `stream`, median of 7 pushes after
- * a warm-up), and records the fastest in the tuning cache under
+ * frequencies and n_lag lags (HIP events on `stream`; after a warm-up the
+ * candidates are timed round-robin, three rounds of two timed pushes each,
+ * and each is ranked by its median), and records the fastest in the tuning
+ * cache under
  * (device architecture, precision, split, n_lag, ceil(log2 n_alpha)).
  * cyc_create consults the cache.  If the environment variable CYC_TUNE_CACHE
  * names a file, the cache is loaded from it on first use and every new entry

@@ -600,30 +600,44 @@ int cyc_autotune(int32_t n_alpha, int32_t n_lag, uint32_t flags, int32_t* best_c
   int n = 0;
   const KernelCfg* c = kernel_cfgs(&n);
   const int prec = (int)(flags & CYC_OP_MASK), split = (flags & CYC_TW_SPLIT) ? 1 : 0;
+  std::vector<int> cand;
+  for (int i = 0; i < n; ++i)
+    if (c[i].prec == prec && c[i].split == split && cyc_set_kernel_cfg(s, i) == CYC_OK) cand.push_back(i);
+  // One timed push of 16 chunks (after a reset) on configuration i; < 0 on failure.
+  auto timed_push = [&](int i) -> double {
+    float t = 0.f;
+    if (cyc_set_kernel_cfg(s, i) != CYC_OK) return -1.0;
+    cyc_reset(s);
+    if (hipEventRecord(e0, st) != hipSuccess || cyc_push(s, x, nsamp, stream) != CYC_OK ||
+        hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+      return -1.0;
+    return (double)t;
+  };
+  // Warm the device up first, then time the candidates round-robin (three
+  // rounds of one untimed and two timed pushes each) and take each one's
+  // median: clock changes while tuning then affect every candidate alike.
+  for (int w = 0; w < 10 && rc == CYC_OK && !cand.empty(); ++w)
+    if (timed_push(cand[0]) < 0) rc = CYC_EDEVICE;
+  std::vector<std::vector<double>> ts(cand.size());
+  for (int round = 0; round < 3 && rc == CYC_OK; ++round)
+    for (size_t k = 0; k < cand.size() && rc == CYC_OK; ++k)
+      for (int rep = 0; rep < 3; ++rep) {
+        const double t = timed_push(cand[k]);
+        if (t < 0) {
+          rc = CYC_EDEVICE;
+          break;
+        }
+        if (rep > 0) ts[k].push_back(t);
+      }
   int best = -1;
   double bms = 1e300;
-  for (int i = 0; i < n && rc == CYC_OK; ++i) {
-    if (c[i].prec != prec || c[i].split != split || cyc_set_kernel_cfg(s, i) != CYC_OK) continue;
-    // median of 7 timed pushes after one warm-up push
-    std::vector<double> ts;
-    for (int rep = 0; rep < 8 && rc == CYC_OK; ++rep) {
-      cyc_reset(s);
-      float t = 0.f;
-      if (hipEventRecord(e0, st) != hipSuccess || cyc_push(s, x, nsamp, stream) != CYC_OK ||
-          hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
-        rc = CYC_EDEVICE;
-        break;
-      }
-      if (rep > 0) ts.push_back((double)t);
-    }
-    if (rc == CYC_OK) {
-      std::sort(ts.begin(), ts.end());
-      const double med = ts[ts.size() / 2];
-      if (med < bms) {
-        bms = med;
-        best = i;
-      }
+  for (size_t k = 0; k < cand.size() && rc == CYC_OK; ++k) {
+    std::sort(ts[k].begin(), ts[k].end());
+    const double med = ts[k][ts[k].size() / 2];
+    if (med < bms) {
+      bms = med;
+      best = cand[k];
     }
   }
   if (e0) (void)hipEventDestroy(e0);
