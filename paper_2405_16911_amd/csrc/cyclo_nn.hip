@@ -6,6 +6,7 @@
 // Activations are kept channel-major, [C][windows * 1024], so each
 // convolution is one matrix product over (windows x positions):
 //   forward  U  = W  (Cout x Cin*7) . col (Cin*7 x N)       col = circular im2col
+//                                                            (read in place, never stored)
 //   backward dW = dU (Cout x N) . col^T,   dcol = W^T . dU,  dX = col2im(dcol)
 // and the head is  Z (B x 1024) = H (B x 65536) . Wh^T  with H the flattened
 // last activation.  All products run on one MFMA GEMM kernel with FP32 or
@@ -27,6 +28,7 @@ namespace nn {
 constexpr int CIN = 3, CH = 64, KW = 7, LEN = 1024, NOUT = 1024, NCONV = 4, WIN = 65536, NSEG = 64;
 constexpr int LABEL_WIN = 1024;  // largest label window (3 coarse bins of fine bins)
 static_assert(NOUT == LEN, "the local layer maps spectral position j to coarse bin j");
+static_assert((LEN & (LEN - 1)) == 0, "circular convolution indices wrap with a mask");
 constexpr int HDIM = CH * LEN;  // flattened head input
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -51,15 +53,19 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
 // global loads are issued before this step's matrix-core work, one barrier per
 // step.  Split K: block z covers k in [z*kchunk, (z+1)*kchunk) and, when part
 // is set, writes its partial product to part[z][M][N] for splitk_reduce_kernel.
-template <int PREC, int TA, int TB, int WMW>
+// With BIM, B holds activations a[ci][ldb] and the GEMM reads their im2col
+// matrix col[ci*KW + kk][b*LEN + t] = a[ci][b*LEN + (t + kk - KW/2) mod LEN]
+// in place of B (op(B) = col for TB = 0, col^T for TB = 1), so the matrix is
+// never written out.
+template <int PREC, int TA, int TB, int WMW, int BIM>
 __global__ __launch_bounds__(256) void gemm_kernel(const float* __restrict__ A,
                                                    const float* __restrict__ B, float* __restrict__ C,
                                                    int M, int N, int K, int lda, int ldb, int ldc,
                                                    int accumulate, int kchunk, float* __restrict__ part) {
   constexpr int BM = 64 * WMW, BN = 64 * (4 / WMW), BK = 32;
-  constexpr int KW = PREC ? BK / 2 : BK;  // LDS words per tile row: BF16 pairs or floats
-  constexpr int LP = KW + 4;              // row pitch in words, rows 16-byte aligned
-  constexpr int NA = BM * KW / 256, NB = BN * KW / 256;  // words each thread stages
+  constexpr int TWD = PREC ? BK / 2 : BK;  // LDS words per tile row: BF16 pairs or floats
+  constexpr int LP = TWD + 4;              // row pitch in words, rows 16-byte aligned
+  constexpr int NA = BM * TWD / 256, NB = BN * TWD / 256;  // words each thread stages
   __shared__ __attribute__((aligned(16))) uint32_t As[2][BM][LP];
   __shared__ __attribute__((aligned(16))) uint32_t Bs[2][BN][LP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -82,15 +88,29 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float* __restrict__ A,
     return ok ? v : 0.f;
   };
   // word w of tile row r holds k = k0 + 2w, k0 + 2w + 1 (BF16) or k = k0 + w (FP32);
-  // thread e stages word (e % KW) of row (e / KW), or, when consecutive rows
+  // thread e stages word (e % TWD) of row (e / TWD), or, when consecutive rows
   // are adjacent in memory (A with TA, B without TB), word (e / rows) of row
   // (e % rows), so that neighbouring threads load neighbouring elements
+  // element op(B)[k][r] (r < N), through the im2col map when BIM
+  auto ldb_ = [&](int r, int k) {
+    const bool ok = r < N && k < kend;
+    int64_t addr;
+    if (BIM) {
+      const int q = TB ? r : k, p = TB ? k : r;  // im2col row and position
+      const int ci = q / KW, kk = q - ci * KW, t = p & (LEN - 1);
+      addr = (int64_t)ci * ldb + (p - t) + ((t + kk - KW / 2) & (LEN - 1));
+    } else {
+      addr = TB ? (int64_t)r * ldb + k : (int64_t)k * ldb + r;
+    }
+    const float v = B[ok ? addr : 0];
+    return ok ? v : 0.f;
+  };
   uint32_t ra[NA], rb[NB];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int e = tid + i * 256;
-      const int r = TA ? e % BM : e / KW, w = TA ? e / BM : e % KW;
+      const int r = TA ? e % BM : e / TWD, w = TA ? e / BM : e % TWD;
       if (PREC)
         ra[i] = pack_bf16(ld(A, lda, TA, m0 + r, M, k0 + 2 * w, kend), ld(A, lda, TA, m0 + r, M, k0 + 2 * w + 1, kend));
       else
@@ -99,23 +119,23 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float* __restrict__ A,
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int e = tid + i * 256;
-      const int r = TB ? e / KW : e % BN, w = TB ? e % KW : e / BN;
+      const int r = TB ? e / TWD : e % BN, w = TB ? e % TWD : e / BN;
       if (PREC)
-        rb[i] = pack_bf16(ld(B, ldb, !TB, n0 + r, N, k0 + 2 * w, kend), ld(B, ldb, !TB, n0 + r, N, k0 + 2 * w + 1, kend));
+        rb[i] = pack_bf16(ldb_(n0 + r, k0 + 2 * w), ldb_(n0 + r, k0 + 2 * w + 1));
       else
-        rb[i] = __float_as_uint(ld(B, ldb, !TB, n0 + r, N, k0 + w, kend));
+        rb[i] = __float_as_uint(ldb_(n0 + r, k0 + w));
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int e = tid + i * 256;
-      As[buf][TA ? e % BM : e / KW][TA ? e / BM : e % KW] = ra[i];
+      As[buf][TA ? e % BM : e / TWD][TA ? e / BM : e % TWD] = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int e = tid + i * 256;
-      Bs[buf][TB ? e / KW : e % BN][TB ? e % KW : e / BN] = rb[i];
+      Bs[buf][TB ? e / TWD : e % BN][TB ? e % TWD : e / BN] = rb[i];
     }
   };
   auto compute = [&](int buf) {
@@ -204,7 +224,7 @@ __global__ void splitk_reduce_kernel(const float* __restrict__ part, float* __re
 // reduced in a second pass.
 hipError_t gemm(int prec, bool ta, bool tb, const float* A, const float* B, float* C, int M, int N, int K,
                 int lda, int ldb, int ldc, bool accumulate, hipStream_t st, float* ws = nullptr,
-                int64_t ws_cap = 0) {
+                int64_t ws_cap = 0, bool bim = false) {
   const int wmw = M <= 64 ? 1 : 2;  // 64 x 256 tiles when one 64-row tile covers M
   const int BM = 64 * wmw, BN = 64 * (4 / wmw);
   const int tiles = ((N + BN - 1) / BN) * ((M + BM - 1) / BM);
@@ -219,15 +239,16 @@ hipError_t gemm(int prec, bool ta, bool tb, const float* A, const float* B, floa
   float* part = S > 1 ? ws : nullptr;
   const dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, S);
   bool launched = false;
-#define GEMM_CASE(P, X, Y, W)                                                                            \
-  if (!launched && prec == P && ta == (bool)X && tb == (bool)Y && wmw == W) {                             \
-    hipLaunchKernelGGL((gemm_kernel<P, X, Y, W>), grid, dim3(256), 0, st, A, B, C, M, N, K, lda, ldb, ldc, \
-                       accumulate ? 1 : 0, kchunk, part);                                                 \
+#define GEMM_CASE(P, X, Y, W, I)                                                                         \
+  if (!launched && prec == P && ta == (bool)X && tb == (bool)Y && wmw == W && bim == (bool)I) {            \
+    hipLaunchKernelGGL((gemm_kernel<P, X, Y, W, I>), grid, dim3(256), 0, st, A, B, C, M, N, K, lda, ldb,    \
+                       ldc, accumulate ? 1 : 0, kchunk, part);                                            \
     launched = true;                                                                                      \
   }
 #define GEMM_CASES(W)                                                                                     \
-  GEMM_CASE(0, 0, 0, W) GEMM_CASE(0, 0, 1, W) GEMM_CASE(0, 1, 0, W) GEMM_CASE(0, 1, 1, W)                 \
-  GEMM_CASE(1, 0, 0, W) GEMM_CASE(1, 0, 1, W) GEMM_CASE(1, 1, 0, W) GEMM_CASE(1, 1, 1, W)
+  GEMM_CASE(0, 0, 0, W, 0) GEMM_CASE(0, 0, 1, W, 0) GEMM_CASE(0, 1, 0, W, 0) GEMM_CASE(0, 1, 1, W, 0)     \
+  GEMM_CASE(1, 0, 0, W, 0) GEMM_CASE(1, 0, 1, W, 0) GEMM_CASE(1, 1, 0, W, 0) GEMM_CASE(1, 1, 1, W, 0)     \
+  GEMM_CASE(0, 0, 0, W, 1) GEMM_CASE(0, 0, 1, W, 1) GEMM_CASE(1, 0, 0, W, 1) GEMM_CASE(1, 0, 1, W, 1)
   GEMM_CASES(1) GEMM_CASES(2)
 #undef GEMM_CASES
 #undef GEMM_CASE
@@ -241,20 +262,6 @@ hipError_t gemm(int prec, bool ta, bool tb, const float* A, const float* B, floa
 // ----------------------------------------------------------------------------- elementwise
 
 inline int nb(int64_t n, int bs = 256) { return (int)((n + bs - 1) / bs); }
-
-// col[(ci*KW + k)][b*LEN + t] = a[ci][b*LEN + (t + k - KW/2) mod LEN]
-__global__ void im2col_kernel(const float* a, float* col, int cin, int nb_) {
-  const int64_t BL = (int64_t)nb_ * LEN;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)cin * KW * BL) return;
-  const int64_t n = i % BL;
-  const int r = (int)(i / BL);
-  const int ci = r / KW, k = r % KW;
-  const int64_t b = n / LEN;
-  const int t = (int)(n % LEN);
-  const int s = (t + k - KW / 2 + LEN) % LEN;
-  col[i] = a[(int64_t)ci * BL + b * LEN + s];
-}
 
 // da[ci][b*LEN + s] = sum_k dcol[(ci*KW + k)][b*LEN + (s - k + KW/2) mod LEN]
 __global__ void col2im_kernel(const float* dcol, float* da, int cin, int nb_) {
@@ -714,7 +721,6 @@ struct cyc_model {
   int step = 0;
   float* u[NCONV] = {};  // pre-activations [CH][B*LEN]
   float* a[NCONV] = {};  // activations
-  float* col = nullptr;  // [CH*KW][B*LEN]
   float* dcol = nullptr;
   float* hbuf = nullptr;  // [B][HDIM]
   float* z = nullptr;     // [B][NOUT]
@@ -744,7 +750,7 @@ int64_t model_nparams() {
 
 void model_free(cyc_model* m) {
   if (!m) return;
-  float* bufs[] = {m->w,  m->g, m->m,  m->v,  m->col, m->dcol,  m->hbuf,
+  float* bufs[] = {m->w,  m->g, m->m,  m->v,  m->dcol,  m->hbuf,
                    m->z,  m->dz, m->da, m->db2, m->ws, m->pfeat, m->pprob, m->rpart};
   for (float* p : bufs) (void)hipFree(p);
   for (int i = 0; i < NCONV; ++i) {
@@ -768,9 +774,9 @@ hipError_t model_forward(cyc_model* m, const float* feat, int n, hipStream_t st)
   const float* in = feat;
   int cin = CIN;
   for (int i = 0; i < NCONV; ++i) {
-    hipLaunchKernelGGL(im2col_kernel, dim3(nb((int64_t)cin * KW * BL)), dim3(256), 0, st, in, m->col, cin, n);
-    hipError_t e = gemm(m->prec, false, false, m->w + m->offW[i], m->col, m->u[i], CH, (int)BL, cin * KW,
-                        cin * KW, (int)BL, (int)BL, false, st, m->ws, m->ws_cap);
+    // u = W . col(in)
+    hipError_t e = gemm(m->prec, false, false, m->w + m->offW[i], in, m->u[i], CH, (int)BL, cin * KW,
+                        cin * KW, (int)BL, (int)BL, false, st, m->ws, m->ws_cap, true);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(bias_relu_kernel, dim3(nb((int64_t)CH * BL)), dim3(256), 0, st, m->u[i],
                        m->w + m->offb[i], m->a[i], CH, BL);
@@ -815,9 +821,9 @@ hipError_t model_backward(cyc_model* m, const float* feat, const float* labels, 
     const float* in = i == 0 ? feat : m->a[i - 1];
     hipLaunchKernelGGL(relu_bwd_kernel, dim3(nb((int64_t)CH * BL)), dim3(256), 0, st, m->da, m->u[i],
                        (int64_t)CH * BL);
-    hipLaunchKernelGGL(im2col_kernel, dim3(nb((int64_t)cin * KW * BL)), dim3(256), 0, st, in, m->col, cin, n);
-    e = gemm(m->prec, false, true, m->da, m->col, m->g + m->offW[i], CH, cin * KW, (int)BL, (int)BL, (int)BL,
-             cin * KW, false, st, m->ws, m->ws_cap);
+    // dW = da . col(in)^T
+    e = gemm(m->prec, false, true, m->da, in, m->g + m->offW[i], CH, cin * KW, (int)BL, (int)BL, (int)BL,
+             cin * KW, false, st, m->ws, m->ws_cap, true);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(rowsum_part_kernel, dim3(CH, RSPLIT), dim3(256), 0, st, m->da, (const float*)nullptr,
                        m->rpart, BL);
@@ -875,7 +881,7 @@ int cyc_model_create(cyc_model** out, int32_t max_batch, uint32_t flags, void* s
   m->np = o;
   const int64_t BL = (int64_t)max_batch * LEN;
   bool ok = dal(&m->w, o) == hipSuccess && dal(&m->g, o) == hipSuccess && dal(&m->m, o) == hipSuccess &&
-            dal(&m->v, o) == hipSuccess && dal(&m->col, (int64_t)CH * KW * BL) == hipSuccess &&
+            dal(&m->v, o) == hipSuccess &&
             dal(&m->dcol, (int64_t)CH * KW * BL) == hipSuccess &&
             dal(&m->hbuf, (int64_t)max_batch * HDIM) == hipSuccess &&
             dal(&m->z, (int64_t)max_batch * NOUT) == hipSuccess &&

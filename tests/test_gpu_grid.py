@@ -124,10 +124,20 @@ def test_edge_cases(cy):
     g.reset()
     g.push(d)
     R2, Rc2, n2 = g.read()
+    # the fold bins are cleared by the first push after a reset, whatever it holds:
+    # two resets, a read of the empty state, a push too short to complete a product
+    g.reset()
+    g.reset()
+    R0, Rc0, n0 = g.read()
+    g.push(d[:3])
+    g.push(d[3:])
+    R3, Rc3, n3 = g.read()
     torch.cuda.synchronize()
     g.close()
-    assert n1 == n2 == x.size - T + 1
+    assert n0 == 0 and not R0.abs().any() and not Rc0.abs().any()
+    assert n1 == n2 == n3 == x.size - T + 1
     assert torch.equal(R1, R2) and torch.equal(Rc1, Rc2)
+    assert torch.equal(R1, R3) and torch.equal(Rc1, Rc3)
     Ro, Rco, _ = cyclic_tables(x, 0.25 + np.arange(A) / A, T)
     assert _err(x, T, R1.cpu().numpy(), Rc1.cpu().numpy(), Ro, Rco) <= TOL
 
