@@ -59,6 +59,7 @@ def test_invalid_arguments_rejected_on_host(L):
     assert L.cyc_create(ctypes.byref(out), a, 0, 4, 0, None) == cyclo.CYC_EINVAL
     assert L.cyc_create(ctypes.byref(out), a, 3, 0, 0, None) == cyclo.CYC_EINVAL
     assert L.cyc_create(ctypes.byref(out), a, 3, 5000, 0, None) == cyclo.CYC_EINVAL
+    assert L.cyc_create(ctypes.byref(out), a, 3, 4097, 0, None) == cyclo.CYC_EINVAL  # T <= 4096
     assert L.cyc_create(ctypes.byref(out), a, 3, 4, 0x100, None) == cyclo.CYC_EINVAL
     assert L.cyc_create(ctypes.byref(out), a, 3, 4, 0x3, None) == cyclo.CYC_EINVAL
     assert L.cyc_create(ctypes.byref(out), a, 3, 4, cyclo.CYC_TW_SPLIT, None) == cyclo.CYC_EUNSUPPORTED

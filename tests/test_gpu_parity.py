@@ -108,6 +108,17 @@ def test_ragged_shapes(cy, flags, T, A):
     assert np.array_equal(R, R2) and np.array_equal(Rc, Rc2)
 
 
+@pytest.mark.parametrize("flags", [0, 1])
+def test_maximum_lag_count(cy, flags):
+    """T = 4096, the largest lag count: 32 lag tiles, two full chunks and a
+    partial one, five cycle frequencies (one alpha tile, ragged)."""
+    T = 4096
+    x = siggen.qpsk_rrc_stream(n=T - 1 + 2 * 4096 + 905, seed=31)
+    alphas = np.array([0.0, 0.1, -0.25, 1 / 3, 0.4999])
+    R, Rc, n, _ = _run(cy, x, alphas, T, flags=flags, splits=[5000, x.size - 5000])
+    _check(x, alphas, T, R, Rc, n, TOL[flags])
+
+
 def test_every_kernel_configuration(cy):
     """Each tile configuration against the oracle; within one precision/split mode
     all configurations give bit-identical tables (same operands, same order)."""
