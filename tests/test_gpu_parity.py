@@ -119,6 +119,25 @@ def test_maximum_lag_count(cy, flags):
     _check(x, alphas, T, R, Rc, n, TOL[flags])
 
 
+@pytest.mark.parametrize("flags", [0, 1])
+def test_many_cycle_frequencies_sampled(cy, flags):
+    """65536 cycle frequencies (1024 alpha tiles, the proposal's fine grid):
+    sampled columns, including the first and last tiles, against the oracle
+    evaluated on those cycle frequencies alone."""
+    T, A = 8, 65536
+    x = siggen.mixed_stream(4, 2, n=2 * 4096 + 300 + T)[0]
+    alphas = -0.5 + np.arange(A) / A
+    R, Rc, n, _ = _run(cy, x, alphas, T, flags=flags)
+    rng = np.random.default_rng(flags)
+    cols = np.unique(np.concatenate([np.arange(64), np.arange(A - 64, A), rng.integers(0, A, size=256)]))
+    Ro, Rco, no = cyclic_tables(x, alphas[cols], T)
+    assert n == no
+    s = scale_per_lag(x, T)
+    e = max(_scaled_err(R[:, cols], Ro, s).max(), _scaled_err(Rc[:, cols], Rco, s).max())
+    print(f"  {cols.size} sampled columns: max scaled error {e:.3e}", flush=True)
+    assert e <= TOL[flags]
+
+
 def test_every_kernel_configuration(cy):
     """Each tile configuration against the oracle; within one precision/split mode
     all configurations give bit-identical tables (same operands, same order)."""
