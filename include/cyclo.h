@@ -234,7 +234,7 @@ int cyc_autotune(int32_t n_alpha, int32_t n_lag, uint32_t flags, int32_t* best_c
  *               (either array, or any entry, may be NULL to skip).
  *   n_used    : host array of n_streams (may be NULL).
  * Errors: as the single-stream calls.  The batch allocates its descriptor
- * tables and workspace at creation (CYC_WORKSPACE_MB, default 1024, bounds the
+ * tables and workspace at creation (CYC_WORKSPACE_MB, default 4096, bounds the
  * partial-sum workspace; larger pushes are processed in several rounds).  The
  * chunk length (CYC_CHUNK) defaults to 4096 products for FP32 operands and
  * 16384 for BF16/FP16.

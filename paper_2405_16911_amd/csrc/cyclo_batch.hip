@@ -338,7 +338,9 @@ int cyc_batch_create(cyc_batch** out, int32_t n_streams, const int64_t* alpha_of
   }
   b->ATMAX = (int)at;
   b->CTMAX = (int)ct;
-  const int64_t ws_bytes = env_i64b("CYC_WORKSPACE_MB", 1024) << 20;
+  // 4 GiB holds one push of the 512-stream benchmark mix in a single round
+  // (1 GiB needed four: BF16 5.2-5.4e13 against 5.5e13 (alpha,tau)*samples/s)
+  const int64_t ws_bytes = env_i64b("CYC_WORKSPACE_MB", 4096) << 20;
   b->part_cap = std::max<int64_t>(2 * (int64_t)b->T * amax, ws_bytes / 8);
   b->E_cap = std::max<int64_t>(amax, b->part_cap / (2 * (int64_t)b->T));
   b->JMAX = 32768;
