@@ -335,8 +335,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; multi-GPU sharding is "
-                                   "a design note, not an implemented path", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the estimator runs and is measured on one GPU only; sharding it "
+                                   "across GPUs is designed but not implemented", "n_gpus": args.gpus}))
         raise SystemExit(2)
 
     forms_wanted = [f for f in args.forms.split(",") if f]

@@ -9,8 +9,9 @@ the selected alphas, fallbacks below the confidence threshold tuned on
 validation windows) must be faster than the full grid at a bounded miss rate,
 while returning the full grid's values at the alphas it evaluates.
 
-The driver runs as a child process so that its window generators (a process
-pool) start before anything in that process touches the GPU.
+The training script (paper_2405_16911_amd/proposal.py) runs as a child
+process so that its window generators (a process pool) start before anything
+in that process touches the GPU.
 """
 import json
 import os
