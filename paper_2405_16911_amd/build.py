@@ -8,6 +8,8 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -16,7 +18,7 @@ LIB = os.path.join(PKG, "libcyclo.so")
 SOURCES = ["cyclo_kernels.hip", "cyclo_runtime.hip", "cyclo_batch.hip", "cyclo_nn.hip", "cyclo_grid.hip", "cyclo_scf.hip", "cyclo_window.hip"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed-FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -30,20 +32,40 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build_library(verbose: bool = False) -> str:
-    """Compiles every HIP source into paper_2405_16911_amd/libcyclo.so; returns its path."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + srcs
-    if verbose:
-        print(" ".join(cmd), flush=True)
+def _run(cmd):
     res = subprocess.run(cmd, capture_output=True, text=True)
     errs = [ln for ln in res.stderr.splitlines() if "packed-fp32-ops" not in ln]
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + "\n".join(errs))
-    if verbose and errs:
-        print("\n".join(errs), file=sys.stderr)
-    os.replace(tmp, LIB)
+    return res.returncode, errs
+
+
+def build_library(verbose: bool = False) -> str:
+    """Compiles every HIP source (one hipcc per file, in parallel) and links
+    paper_2405_16911_amd/libcyclo.so; returns its path."""
+    inc = ["-I", os.path.join(ROOT, "include")]
+    with tempfile.TemporaryDirectory(prefix="cyclo_build_") as tmpd:
+        objs, cmds = [], []
+        for src in SOURCES:
+            obj = os.path.join(tmpd, src + ".o")
+            objs.append(obj)
+            cmds.append([hipcc()] + HIPCC_FLAGS + inc + ["-c", os.path.join(CSRC, src), "-o", obj])
+        if verbose:
+            for c in cmds:
+                print(" ".join(c), flush=True)
+        with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
+            results = list(ex.map(_run, cmds))
+        for (rc, errs), src in zip(results, SOURCES):
+            if rc != 0:
+                raise RuntimeError(f"hipcc failed on {src}:\n" + "\n".join(errs))
+            if verbose and errs:
+                print("\n".join(errs), file=sys.stderr)
+        tmp = LIB + ".tmp"
+        link = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+        if verbose:
+            print(" ".join(link), flush=True)
+        rc, errs = _run(link)
+        if rc != 0:
+            raise RuntimeError("link failed:\n" + "\n".join(errs))
+        os.replace(tmp, LIB)
     return LIB
 
 
