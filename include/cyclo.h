@@ -53,8 +53,7 @@ extern "C" {
  * creation, overrides it; batches default to 16384 for BF16/FP16). */
 #define CYC_OP_FP32   0x0u   /* FP32 operands (default)                       */
 #define CYC_OP_BF16   0x1u   /* BF16 operands                                 */
-#define CYC_OP_FP16   0x2u   /* FP16 operands (without CYC_TW_SPLIT the        */
-                             /* modulated operand is formed in FP16 arithmetic) */
+#define CYC_OP_FP16   0x2u   /* FP16 operands                                 */
 #define CYC_OP_MASK   0x3u
 /* Split the modulated operand conj(x[n])exp(-j2pi alpha n) (the one that holds
  * the twiddle) into hi + lo parts of the operand precision: two matrix-core

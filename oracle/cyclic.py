@@ -322,3 +322,24 @@ def scale_per_lag(x, T: int) -> np.ndarray:
     if N == 0:
         return np.zeros(T)
     return np.array([np.dot(x[t: t + N], x[:N]) / N for t in range(T)])
+
+
+def roundoff_ratio_per_lag(x, T: int) -> np.ndarray:
+    """r_t = sqrt(sum_n |x[n+t]|^2 |x[n]|^2) / sum_n |x[n+t]| |x[n]|, n < N_used.
+
+    Ratio of the root-sum-square of the lag products' magnitudes to their sum:
+    independent roundings of relative size u in each product give a scaled
+    error of about u * r_t (a random walk), against u for roundings that all
+    push the same way.  Equals 1/sqrt(N_used) for a constant-modulus signal.
+    Test infrastructure for the reduced-precision tolerances; zeros when
+    N_used = 0.
+    """
+    x = np.abs(np.asarray(x).astype(np.complex128).reshape(-1))
+    N = max(0, x.size - T + 1)
+    if N == 0:
+        return np.zeros(T)
+    out = np.empty(T)
+    for t in range(T):
+        m = x[t: t + N] * x[:N]
+        out[t] = np.sqrt(np.dot(m, m)) / m.sum()
+    return out

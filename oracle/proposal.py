@@ -141,6 +141,93 @@ def adamw_step(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, wd=1e-2):
         p[k] = p[k] - lr * (mh / (np.sqrt(vh) + eps) + wd * p[k])
 
 
+# ----------------------------------------------------------------------------- rounding-noise model of the GPU network
+
+
+def perturbed_pass(p, X, y, u, rng, n_conv=4):
+    """One draw of the rounding-noise model of the reduced-precision network
+    (test infrastructure).
+
+    The GPU rounds both operands of every matrix product (convolutions, head,
+    backward products) to the operand precision and keeps everything else in
+    FP32.  This pass is the FP64 network with each such operand value v
+    replaced by v (1 + d), d uniform in [-u, u] and drawn once per value per
+    pass (a value that feeds several products is rounded the same way in each,
+    as on the GPU); the backward ReLU masks with the pass's own
+    pre-activations.  Uniform relative errors in [-u, u] have mean square u^2/3,
+    which is at least that of round-to-nearest (half an ulp uniform, at most
+    u^2/3 relative).  Returns (probabilities, gradient dict).
+    """
+    def rnd(v):
+        return v * (1.0 + rng.uniform(-u, u, size=v.shape)) if u > 0 else v
+
+    B = X.shape[0]
+    Wq = {i: rnd(p[f"W{i}"]) for i in range(n_conv)}
+    Whq = rnd(p["Wh"])
+    acts, aq, pre = [X], [rnd(X)], []
+    for i in range(n_conv):
+        u_ = conv_circ(aq[i], Wq[i], p[f"b{i}"])
+        pre.append(u_)
+        a = np.maximum(u_, 0.0)
+        acts.append(a)
+        aq.append(rnd(a))
+    a4 = acts[-1]
+    hq = aq[-1].reshape(B, -1)
+    z = hq @ Whq.T + p["bh"][None, :] + np.einsum("c,ncj->nj", p["Wl"], a4)
+    prob = sigmoid(z)
+    dz = (prob - y) / z.size
+    dzq = rnd(dz)
+    g = {"Wh": dzq.T @ hq, "bh": dz.sum(axis=0), "Wl": np.einsum("nj,ncj->c", dz, a4)}
+    da = (dzq @ Whq).reshape(a4.shape) + p["Wl"][None, :, None] * dz[:, None, :]
+    for i in reversed(range(n_conv)):
+        du = da * (pre[i] > 0)
+        duq = rnd(du)
+        dx, g[f"W{i}"], _ = conv_circ_backward(aq[i], Wq[i], duq)
+        g[f"b{i}"] = du.sum(axis=(0, 2))
+        if i > 0:
+            da = dx
+    return prob, g
+
+
+def rounding_noise_scale(p, X, y, u, trials, seed, n_conv=4):
+    """Root-mean-square deviation from the exact FP64 values, per element, of
+    the probabilities and gradients over `trials` draws of perturbed_pass."""
+    rng = np.random.default_rng(seed)
+    z, cache = forward(p, X, n_conv)
+    prob0 = sigmoid(z)
+    g0 = backward(p, cache, z, y, n_conv)
+    sp = np.zeros_like(prob0)
+    sg = {k: np.zeros_like(v) for k, v in g0.items()}
+    for _ in range(trials):
+        prob, g = perturbed_pass(p, X, y, u, rng, n_conv)
+        sp += (prob - prob0) ** 2
+        for k in sg:
+            sg[k] += (g[k] - g0[k]) ** 2
+    return np.sqrt(sp / trials), {k: np.sqrt(v / trials) for k, v in sg.items()}
+
+
+def gradient_magnitude_sums(p, X, y, n_conv=4):
+    """Sum of |terms| of the last sum behind each gradient element (and of the
+    logit behind each probability): the scale of FP32 accumulation error."""
+    B = X.shape[0]
+    z, cache = forward(p, X, n_conv)
+    acts, pre = cache["acts"], cache["pre"]
+    a4 = np.abs(acts[-1])
+    h = a4.reshape(B, -1)
+    mz = h @ np.abs(p["Wh"]).T + np.abs(p["bh"])[None, :] + np.einsum("c,ncj->nj", np.abs(p["Wl"]), a4)
+    prob = sigmoid(z)
+    dz = (prob - y) / z.size
+    m = {"Wh": np.abs(dz).T @ h, "bh": np.abs(dz).sum(axis=0), "Wl": np.einsum("nj,ncj->c", np.abs(dz), a4)}
+    da = (dz @ p["Wh"]).reshape(acts[-1].shape) + p["Wl"][None, :, None] * dz[:, None, :]
+    for i in reversed(range(n_conv)):
+        du = da * (pre[i] > 0)
+        m[f"W{i}"] = conv_circ_backward(np.abs(acts[i]), np.abs(p[f"W{i}"]), np.abs(du))[1]
+        m[f"b{i}"] = np.abs(du).sum(axis=(0, 2))
+        if i > 0:
+            da = conv_circ_backward(acts[i], p[f"W{i}"], du)[0]
+    return mz, m
+
+
 # ----------------------------------------------------------------------------- labels and selection
 
 
@@ -190,10 +277,14 @@ def select(prob, k: int = 16, width: int = 2, zero_bin: int | None = None):
     """Top-k bins (ties -> lower index), each widened by +-width circularly, sorted.
 
     Returns (selected bins, confidence = 1 - max probability outside the set).
+    NaN bins are never among the top k, and a window with any non-finite
+    probability has confidence 0 (it always falls back to the full grid): the
+    confidence rule is defined for probabilities only.
     """
     prob = np.asarray(prob, dtype=np.float64)
     n = prob.size
     order = np.lexsort((np.arange(n), -prob))   # descending prob, then ascending index
+    order = [i for i in order if not np.isnan(prob[i])]
     sel = set()
     for i in order[:k]:
         for d in range(-width, width + 1):
@@ -204,4 +295,6 @@ def select(prob, k: int = 16, width: int = 2, zero_bin: int | None = None):
     mask = np.ones(n, bool)
     mask[sel] = False
     conf = 1.0 - (prob[mask].max() if mask.any() else 0.0)
+    if not np.all(np.isfinite(prob)):
+        conf = 0.0
     return sel, conf

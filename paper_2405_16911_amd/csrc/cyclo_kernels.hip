@@ -211,26 +211,6 @@ __device__ __forceinline__ void modulate(const float2* xs, float2 hv, const floa
   }
 }
 
-// The same for FP16 operands, in packed FP16 arithmetic (two components per
-// instruction): W = H Lo, t = Re(x) W, v = Im(x) (Im W, -Re W), Y = t + v,
-// Yc = t - v, with every multiply-add written as an explicit FMA so every
-// kernel rounds it identically.  hh = H, hs = (-Im H, Im H); lo16 = Lo in FP16.
-typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
-template <int G>
-__device__ __forceinline__ void modulate_h2(const float2* xs, h2_t hh, h2_t hs, const h2_t (&lo16)[G],
-                                            uint32_t (&py)[G], uint32_t (&pyc)[G]) {
-#pragma unroll
-  for (int g = 0; g < G; ++g) {
-    const float2 xv = xs[g];
-    const h2_t xr = {(_Float16)xv.x, (_Float16)xv.x}, xi = {(_Float16)xv.y, (_Float16)xv.y};
-    const h2_t w = __builtin_elementwise_fma(hs, lo16[g].yx, hh.xx * lo16[g]);
-    const h2_t t = xr * w;
-    const h2_t sw = {w.y, -w.x};
-    py[g] = __builtin_bit_cast(uint32_t, __builtin_elementwise_fma(xi, sw, t));
-    pyc[g] = __builtin_bit_cast(uint32_t, __builtin_elementwise_fma(-xi, sw, t));
-  }
-}
-__device__ __forceinline__ h2_t to_h2(float2 v) { return (h2_t){(_Float16)v.x, (_Float16)v.y}; }
 
 // Common per-workgroup set-up.
 struct Tile {
@@ -412,16 +392,9 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
   const int ga = tid % AW, gj = (tid / AW) * G;
   const int galpha = tl.alpha0 + ga;
   const bool aval = galpha < a.A;
-  // FP16 operands without the split: the modulated operands are formed in
-  // packed FP16 arithmetic (a few FP16 roundings, inside the FP16 bound)
-  constexpr bool HALF_MOD = PREC == PREC_F16 && !SPLIT;
   float2 lo[G];
-  h2_t lo16[G];
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-    lo[g] = aval ? a.Lo[(int64_t)galpha * KS + gj + g] : make_float2(0.f, 0.f);
-    lo16[g] = to_h2(lo[g]);
-  }
+  for (int g = 0; g < G; ++g) lo[g] = aval ? a.Lo[(int64_t)galpha * KS + gj + g] : make_float2(0.f, 0.f);
   const float2* Hrow = a.H + (int64_t)(aval ? galpha : 0) * tl.nsteps;
   auto hptr = [&](int ks) { return Hrow + min(ks, tl.nsteps - 1); };
 
@@ -455,10 +428,7 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
     }
     // modulated operands
     uint32_t py[NB][G], pyc[NB][G];
-    if (HALF_MOD) {
-      const h2_t hh = to_h2(hv), hs = {-hh.y, hh.y};
-      modulate_h2<G>(&Xy[buf][gj], hh, hs, lo16, py[0], pyc[0]);
-    } else {
+    {
       float2 y[G], yc[G];
       modulate<G>(&Xy[buf][gj], hv, lo, y, yc);
 #pragma unroll
@@ -747,13 +717,7 @@ __global__ __launch_bounds__(64, 1) void contract_rg(ContractArgs a) {
 #pragma unroll
     for (int nb = 0; nb < NA; ++nb) {
       uint32_t py[NB][4], pyc[NB][4];
-      if (PREC == PREC_F16 && !SPLIT) {  // as the LDS kernels' FP16 path
-        const h2_t hh = to_h2(hv[nb]), hs = {-hh.y, hh.y};
-        h2_t l16[4];
-#pragma unroll
-        for (int g = 0; g < 4; ++g) l16[g] = to_h2(lo[nb][kb][g]);
-        modulate_h2<4>(xs[kb], hh, hs, l16, py[0], pyc[0]);
-      } else {
+      {
         float2 y[4], yc[4];
         modulate<4>(xs[kb], hv[nb], lo[nb][kb], y, yc);
 #pragma unroll

@@ -609,8 +609,9 @@ __global__ void coarse_label_kernel(const float2* R, const float2* Rc, int T, in
   if (threadIdx.x == 0) label[c] = hit ? 1.f : 0.f;
 }
 
-// Per window: top-k bins of prob (ties -> lower index), widened by +-width
-// circularly, plus zero_bin; conf = 1 - max prob outside the selection.
+// Per window: top-k bins of prob (ties -> lower index; NaN bins are never
+// chosen), widened by +-width circularly, plus zero_bin; conf = 1 - max prob
+// outside the selection, or 0 when any probability is NaN or infinite.
 __global__ __launch_bounds__(256) void select_kernel(const float* prob, int n, int topk, int width,
                                                      int zero_bin, uint8_t* sel, float* conf) {
   __shared__ float p[NOUT];
@@ -656,17 +657,20 @@ __global__ __launch_bounds__(256) void select_kernel(const float* prob, int n, i
   }
   __syncthreads();
   float mx = 0.f;
+  int bad = 0;
   for (int i = tid; i < NOUT; i += 256) {
     sel[(int64_t)w * NOUT + i] = s8[i];
     if (!s8[i]) mx = fmaxf(mx, p[i]);
+    if (!(fabsf(p[i]) <= 3.402823466e38f)) bad = 1;  // NaN or infinite
   }
   rv[tid] = mx;
-  __syncthreads();
+  bad = __syncthreads_or(bad);
   for (int k = 128; k > 0; k >>= 1) {
     if (tid < k) rv[tid] = fmaxf(rv[tid], rv[tid + k]);
     __syncthreads();
   }
-  if (tid == 0) conf[w] = 1.f - rv[0];
+  // a window with a non-finite probability has no confidence: it falls back
+  if (tid == 0) conf[w] = bad ? 0.f : 1.f - rv[0];
 }
 
 // Per window: the selected coarse bins in ascending order (bins[w][0 .. n)),

@@ -12,14 +12,12 @@ import os
 import numpy as np
 import pytest
 
-from oracle.cyclic import cyclic_tables, scale_per_lag
+from _bounds import check_cells
+from oracle.cyclic import cyclic_tables
 from paper_2405_16911_amd import siggen
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-
-TOL = {0: 1e-5, 1: 2.0 ** -7, 2: 2.0 ** -10}
-
 
 @pytest.fixture(scope="module")
 def cy():
@@ -85,13 +83,12 @@ def test_batch_matches_oracle_and_single_states(cy, flags):
         if no == 0:
             assert not np.abs(Rs[s]).any() and not np.abs(Rcs[s]).any()
             continue
-        sc = scale_per_lag(x, T)[:, None]
-        e = max(np.max(np.abs(Rs[s] - Ro) / sc), np.max(np.abs(Rcs[s] - Rco) / sc))
-        assert e <= TOL[flags], (s, e)
-        # single state, same samples, the batch's kernel configuration and chunk
-        # length (16-bit operands: 16384 products per chunk in a batch, 4096 in a
-        # single state by default)
+        # 16-bit operands: 16384 products per chunk in a batch, 4096 in a single
+        # state by default
         chunk = 4096 if flags == 0 else 16384
+        check_cells(x, T, flags, chunk, Rs[s], Rcs[s], Ro, Rco, f"stream {s} L={x.size} A={al.size}")
+        # single state, same samples, the batch's kernel configuration and chunk
+        # length
         st = _with_env({"CYC_CHUNK": chunk}, lambda: cy.CyclicStream(al, T, flags))
         assert st.query()["chunk"] == chunk
         st.set_kernel_cfg(qs[-1]["kernel_cfg"])
@@ -131,3 +128,54 @@ def test_batch_reset_and_reuse(cy):
     for a, c in zip(R1 + Rc1, R2 + Rc2):
         assert torch.equal(a, c)
     b.close()
+
+
+def _long_workload(seed, T):
+    """Streams of 2^15..2^18 samples (several 16384-product chunks each) with
+    alpha sets up to 2048 bins, most of them not powers of two."""
+    xs, alists = [], []
+    rng = np.random.default_rng(seed)
+    for s, A in enumerate([2048, 1500, 777, 64, 1234, 333]):
+        L = int(2 ** rng.uniform(15, 18))
+        xs.append(siggen.mixed_stream(seed, s, n=L)[0])
+        alists.append(-0.5 + np.arange(A) / A)
+    return xs, alists
+
+
+@pytest.mark.parametrize("flags", [1, 2, 1 | 4, 2 | 4])
+def test_batch_16bit_committed_chunks(cy, flags):
+    """16-bit batches whose pushes commit whole 16384-product chunks: against the
+    oracle on sampled columns (every cell within its bound), bitwise against
+    single states with the same chunk length and kernel configuration, and
+    bitwise across round splits (a 16 MiB workspace: several rounds per push)
+    and graph replay vs direct launches."""
+    T = 64
+    xs, alists = _long_workload(21, T)
+    Rs, Rcs, nu, qs = _run_batch(cy, xs, alists, T, flags, splits=3, env={"CYC_WORKSPACE_MB": 16})
+    print(f"  rounds per push {[q['rounds'] for q in qs]}, graph {qs[-1]['graph']}", flush=True)
+    assert max(q["rounds"] for q in qs) > 1
+    direct = _run_batch(cy, xs, alists, T, flags, splits=3, env={"CYC_WORKSPACE_MB": 16, "CYC_NO_GRAPH": 1})
+    one = _run_batch(cy, xs, alists, T, flags, splits=1)
+    for s in range(len(xs)):
+        for other in (direct, one):
+            assert np.array_equal(Rs[s], other[0][s]) and np.array_equal(Rcs[s], other[1][s]), s
+    rng = np.random.default_rng(flags)
+    for s, (x, al) in enumerate(zip(xs, alists)):
+        A = al.size
+        assert (x.size - T + 1) // 16384 >= 1
+        cols = np.unique(np.concatenate([np.arange(min(8, A)), np.arange(max(0, A - 8), A),
+                                         rng.integers(0, A, size=32), [A // 2, A // 4, (3 * A) // 4]]))
+        Ro, Rco, no = cyclic_tables(x, al[cols], T)
+        assert nu[s] == no
+        check_cells(x, T, flags, 16384, Rs[s][:, cols], Rcs[s][:, cols], Ro, Rco,
+                    f"stream {s} L={x.size} A={A} ({cols.size} columns)")
+        st = _with_env({"CYC_CHUNK": 16384}, lambda: cy.CyclicStream(al, T, flags))
+        st.set_kernel_cfg(qs[-1]["kernel_cfg"])
+        d = torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+        st.push(d[:x.size // 3])
+        st.push(d[x.size // 3:])
+        R1, Rc1, n1 = st.read()
+        torch.cuda.synchronize()
+        st.close()
+        assert n1 == nu[s]
+        assert np.array_equal(R1.cpu().numpy(), Rs[s]) and np.array_equal(Rc1.cpu().numpy(), Rcs[s]), s

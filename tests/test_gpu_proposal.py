@@ -3,12 +3,14 @@
 Tolerances: spectra (standardised log, FP32 FFT) <= 5e-3 absolute; network
 probabilities, gradients and one AdamW step with FP32 operands: relative L2
 error per tensor <= 1e-5 (probabilities) / 2e-5 (gradients) / 1e-3 (the step).
-BF16 operands: probabilities and head gradients (dense, bias, local) relative
-L2 <= 2e-2; the convolution-layer gradients pass every operand rounding
-(u = 2^-8) through up to four backward products whose sums cancel heavily for
-random labels, so they are held to relative L2 <= 1e-1 and to the gradient
-direction (cosine >= 0.995); the FP32-operand run of the same kernels pins the
-arithmetic.
+BF16 operands: the oracle's rounding-noise model (oracle.proposal.
+perturbed_pass: every operand of every matrix product perturbed by a relative
+error uniform in +-2^-8, as often as the GPU rounds it) gives each probability
+and gradient element a root-mean-square deviation s over 24 draws; each tensor
+must satisfy |err|^2 <= 4 |s|^2 and each element |err| <= 10 s + 1e-4 M (M: the
+sum of |terms| of its last sum, an FP32 accumulation floor).  Uniform errors
+overstate round-to-nearest's mean square, so the expected energy ratio is
+about 0.5 (pinned on the CPU against an emulated BF16 network).
 Selection and labels are bit-exact (the label kernel is fed the oracle's own
 tables, rounded to complex64).
 """
@@ -73,8 +75,8 @@ def test_spectra_match_oracle(cy):
         assert err.max() < 5e-3
 
 
-@pytest.mark.parametrize("flags,tol_g,tol_p", [(0, 2e-5, 1e-5), (1, 2e-2, 2e-2)])
-def test_forward_and_gradients(cy, flags, tol_g, tol_p):
+@pytest.mark.parametrize("flags", [0, 1])
+def test_forward_and_gradients(cy, flags):
     p = _params(1)
     rng = np.random.default_rng(2)
     B = 2
@@ -88,21 +90,33 @@ def test_forward_and_gradients(cy, flags, tol_g, tol_p):
     feat = torch.from_numpy(np.ascontiguousarray(X.transpose(1, 0, 2)).astype(np.float32)).to("cuda")
     lab = torch.from_numpy(y.astype(np.float32)).to("cuda")
     prob = m.forward(feat).cpu().numpy().astype(np.float64)
-    assert _rel(prob, P.sigmoid(z)) <= tol_p
     gg, gl = m.gradients(feat, lab)
     gg = _unflat(gg.cpu().numpy().astype(np.float64), p)
     m.close()
-    assert abs(gl - loss) <= tol_p * abs(loss)
-    errs = {k: _rel(gg[k], g[k]) for k in KEYS}
-    coss = {k: float(np.dot(gg[k].ravel(), g[k].ravel()) / (np.linalg.norm(gg[k]) * np.linalg.norm(g[k]) + 1e-300))
-            for k in KEYS}
-    for k in KEYS:
-        print(f"  {k}: rel {errs[k]:.2e} cos {coss[k]:.6f}", flush=True)
-    for k in KEYS:
-        conv = flags == 1 and k not in ("Wh", "bh", "Wl")
-        assert errs[k] <= (1e-1 if conv else tol_g), k
-        if flags == 1:
-            assert coss[k] >= 0.995, k
+    got = dict(gg, prob=prob)
+    ref = dict(g, prob=P.sigmoid(z))
+    if flags == 0:
+        assert abs(gl - loss) <= 1e-5 * abs(loss)
+        for k in ["prob"] + KEYS:
+            e = _rel(got[k], ref[k])
+            print(f"  {k}: rel {e:.2e}", flush=True)
+            assert e <= (1e-5 if k == "prob" else 2e-5), k
+        return
+    sp, sg = P.rounding_noise_scale(p, X, y, 2.0 ** -8, trials=24, seed=7)
+    mz, mg = P.gradient_magnitude_sums(p, X, y)
+    sg["prob"], mg["prob"] = sp, mz
+    for k in ["prob"] + KEYS:
+        err = np.abs(got[k] - ref[k])
+        q = float(np.sum(err ** 2) / np.sum(sg[k] ** 2))
+        worst = float(np.max(err / (10 * sg[k] + 1e-4 * mg[k] + 1e-300)))
+        print(f"  {k}: rel {_rel(got[k], ref[k]):.2e} energy ratio {q:.3f} worst element {worst:.3f}", flush=True)
+        assert q <= 4.0 and worst <= 1.0, k
+    # the loss moves by (p - y) dz / n per logit, dz = dp / (p (1 - p)): ten times
+    # the noise that the probabilities' model spread implies
+    pr = P.sigmoid(z)
+    s_loss = np.sqrt(np.sum(((pr - y) / (pr * (1 - pr)) * sp) ** 2)) / pr.size
+    print(f"  loss: error {abs(gl - loss):.2e}, model scale {s_loss:.2e}", flush=True)
+    assert abs(gl - loss) <= 10 * s_loss + 1e-6 * abs(loss)
 
 
 def test_adamw_step_fp32(cy):
@@ -142,6 +156,30 @@ def test_selection_matches_oracle(cy):
         s_ref, c_ref = P.select(prob[i].astype(np.float64), k=16, width=2, zero_bin=512)
         assert list(np.nonzero(sel[i])[0]) == list(s_ref), i
         assert abs(conf[i] - c_ref) < 1e-6
+
+
+def test_selection_falls_back_on_non_finite_probabilities(cy):
+    # a diverged network (NaN outputs) must not look confident
+    rng = np.random.default_rng(6)
+    prob = rng.random((4, 1024)).astype(np.float32) * 0.5
+    prob[0, :] = np.nan                      # every bin NaN
+    prob[1, 17] = np.nan                     # one NaN bin
+    prob[2, [5, 900]] = np.inf               # infinite bins
+    sel, conf = cy.cyc_select(torch.from_numpy(prob).to("cuda"), topk=16, width=2, zero_bin=512)
+    sel, conf = sel.cpu().numpy(), conf.cpu().numpy()
+    for i in range(4):
+        s_ref, c_ref = P.select(prob[i].astype(np.float64), k=16, width=2, zero_bin=512)
+        assert list(np.nonzero(sel[i])[0]) == list(s_ref), i
+        assert conf[i] == c_ref, i
+    assert conf[0] == 0 and conf[1] == 0 and conf[2] == 0 and conf[3] > 0
+    m = cy.ProposalModel(4)
+    try:
+        x = torch.zeros(2 * cy.WINDOW, dtype=torch.complex64, device="cuda")
+        x[5] = float("nan")                  # a non-finite sample in the first window
+        bins, nb, conf, fb = m.propose(x, theta=0.5)
+        assert fb.cpu().tolist()[0] == 1 and conf.cpu().tolist()[0] == 0.0
+    finally:
+        m.close()
 
 
 @pytest.mark.parametrize("A,n_coarse,zero_bin", [(4096, 64, 32), (4095, 63, 31)])

@@ -16,6 +16,9 @@ pin actually bites.
 * ``lag_window('hann')`` (the cyclic spectrum's lag window): hand values at
   M = 3 and SciPy's symmetric Hann window of length 2M + 3 without its zero
   end points.
+* ``roundoff_ratio_per_lag`` (the random-walk factor of the reduced-precision
+  bounds): 1/sqrt(N_used) for constant modulus, a hand-summed case, and the
+  root-mean-square error of simulated independent roundings.
 * ``adamw_step``: ``torch.optim.AdamW`` in float64 over several steps (bias
   correction at t >= 2, decoupled weight decay).
 * ``bce_loss``: ``torch.nn.functional.binary_cross_entropy_with_logits``.
@@ -27,6 +30,46 @@ import torch
 
 from oracle import cyclic as C
 from oracle import proposal as P
+
+# ----------------------------------------------------------------------------- roundoff_ratio_per_lag
+
+
+def test_roundoff_ratio_constant_modulus_is_inverse_sqrt_n():
+    rng = np.random.default_rng(13)
+    x = 2.5 * np.exp(2j * np.pi * rng.random(1000))
+    r = C.roundoff_ratio_per_lag(x, 7)
+    assert np.max(np.abs(r * np.sqrt(1000 - 7 + 1) - 1.0)) < 1e-14
+
+
+def test_roundoff_ratio_hand_summed():
+    # |x| = 1, 2, 3, 4; T = 2 -> N_used = 3
+    x = np.array([1.0, 2j, -3.0, 4.0 + 0j])
+    r = C.roundoff_ratio_per_lag(x, 2)
+    assert r[0] == pytest.approx(np.sqrt(1 + 16 + 81) / (1 + 4 + 9), rel=1e-15)
+    assert r[1] == pytest.approx(np.sqrt(4 + 36 + 144) / (2 + 6 + 12), rel=1e-15)
+    assert C.roundoff_ratio_per_lag(x, 5).tolist() == [0.0] * 5
+
+
+def test_roundoff_ratio_predicts_a_simulated_random_rounding():
+    # relative errors uniform in +-u on each component of each product: the
+    # scaled error of the sum has root mean square u * sqrt(2/3) * r_t
+    rng = np.random.default_rng(14)
+    x = (rng.standard_normal(4000) + 1j * rng.standard_normal(4000)) * (0.5 + rng.random(4000))
+    T, u = 3, 2.0 ** -8
+    r = C.roundoff_ratio_per_lag(x, T)
+    N = x.size - T + 1
+    for t in range(T):
+        p = x[t: t + N] * np.conj(x[:N])
+        w = np.exp(-2j * np.pi * 0.137 * np.arange(N))
+        q = p * w
+        errs = []
+        for _ in range(400):
+            d = q.real * rng.uniform(-u, u, N) + 1j * q.imag * rng.uniform(-u, u, N)
+            errs.append(abs(d.sum()) / np.abs(p).sum())
+        rms = np.sqrt(np.mean(np.square(errs)))
+        # uniform relative errors: E d^2 = u^2 |q|^2 / 3, i.e. sqrt(1/3) per rounding
+        assert rms == pytest.approx(u * np.sqrt(1 / 3) * r[t], rel=0.15)
+
 
 # ----------------------------------------------------------------------------- scale_per_lag
 

@@ -100,6 +100,22 @@ def test_selection_ties_wrap_and_zero_bin():
     assert 30 in sel2 and 31 in sel2 and conf2 == 1.0
 
 
+def test_selection_non_finite_probabilities_fall_back():
+    p = np.zeros(32)
+    p[[3, 20]] = 0.8
+    p[7] = np.nan
+    sel, conf = P.select(p, k=2, width=0)
+    assert list(sel) == [3, 20] and conf == 0.0   # NaN never chosen; no confidence
+    sel, conf = P.select(np.full(8, np.nan), k=2, width=1, zero_bin=4)
+    assert list(sel) == [4] and conf == 0.0
+    q = p.copy()
+    q[7] = np.inf
+    sel, conf = P.select(q, k=1, width=0)
+    assert list(sel) == [7] and conf == 0.0
+    q[7] = 0.1
+    assert P.select(q, k=2, width=0)[1] == pytest.approx(0.9)
+
+
 def test_labels_exclude_power_bin():
     rng = np.random.default_rng(3)
     A, n_coarse = 256, 16
@@ -152,3 +168,99 @@ def test_peak_rule_noise_scale_is_rayleigh():
     R = s * (rng.standard_normal((2, 200000)) + 1j * rng.standard_normal((2, 200000)))
     frac = P.peak_cells(R, 1000, thresh=3.0).mean()
     assert abs(frac - np.exp(-4.5)) < 0.1 * np.exp(-4.5)
+
+
+# ----------------------------------------------------------------------------- running-error bound of the network
+
+
+def _bf16(v):
+    """Round to BF16 (nearest, ties to even) from the FP32 value the GPU holds."""
+    b = np.asarray(v, dtype=np.float64).astype(np.float32).view(np.uint32).astype(np.uint64)
+    r = ((b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
+
+
+def _f32(v):
+    return np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def _emulated_bf16_gradients(p, X, y, n_conv=4):
+    """The network with BF16 operands at every matrix product and FP32 results,
+    in the GPU's order of steps (a NumPy emulation, for pinning the bound)."""
+    B, L = X.shape[0], X.shape[2]
+    q = {k: _bf16(v) for k, v in p.items()}
+    acts, pre = [X], []
+    a = X
+    for i in range(n_conv):
+        u = _f32(P.conv_circ(_bf16(a), q[f"W{i}"], np.zeros(p[f"W{i}"].shape[0])))
+        u = _f32(u + p[f"b{i}"][None, :, None])
+        pre.append(u)
+        a = np.maximum(u, 0.0)
+        acts.append(a)
+    h = a.reshape(B, -1)
+    z = _f32(_bf16(h) @ q["Wh"].T)
+    z = _f32(z + _f32(np.einsum("c,ncj->nj", p["Wl"], a)))
+    z = _f32(z + p["bh"][None, :])
+    prob = _f32(1.0 / (1.0 + np.exp(-z)))
+    dz = _f32(_f32(prob - y) / z.size)
+    g = {"Wh": _f32(_bf16(dz).T @ _bf16(h)), "bh": _f32(dz.sum(axis=0)),
+         "Wl": _f32(np.einsum("nj,ncj->c", dz, a))}
+    dh = _f32(_bf16(dz) @ q["Wh"])
+    da = _f32(dh.reshape(a.shape) + p["Wl"][None, :, None] * dz[:, None, :])
+    for i in reversed(range(n_conv)):
+        du = da * (pre[i] > 0)
+        g[f"W{i}"] = _f32(P.conv_circ_backward(_bf16(acts[i]), q[f"W{i}"], _bf16(du))[1])
+        g[f"b{i}"] = _f32(du.sum(axis=(0, 2)))
+        if i > 0:
+            da = _f32(P.conv_circ_backward(acts[i], q[f"W{i}"], _bf16(du))[0])
+    return prob, g
+
+
+def _small_net(seed):
+    rng = np.random.default_rng(seed)
+    p = P.init_params(rng, C_in=3, C=8, K=7, L=64, n_out=64)
+    for k in p:
+        if k.startswith("b"):
+            p[k] = rng.standard_normal(p[k].shape) * 0.05
+        p[k] = _f32(p[k])
+    X = _f32(rng.standard_normal((3, 3, 64)))
+    y = (rng.random((3, 64)) < 0.1).astype(np.float64)
+    return p, X, y
+
+
+def _noise_check(p, X, y, prob_e, g_e, u, trials=24, seed=0):
+    """Per-tensor energy ratio Q = |err|^2 / |model rms|^2 and the worst
+    per-element ratio err / (10 model rms + FP32 floor) of an emulated run."""
+    z, cache = P.forward(p, X)
+    g = P.backward(p, cache, z, y)
+    sp, sg = P.rounding_noise_scale(p, X, y, u, trials, seed)
+    mz, mg = P.gradient_magnitude_sums(p, X, y)
+    out = {}
+    for k, got, ref, s, m in [("prob", prob_e, P.sigmoid(z), sp, mz)] + [(k, g_e[k], g[k], sg[k], mg[k]) for k in g]:
+        err = np.abs(got - ref)
+        q = float(np.sum(err ** 2) / max(np.sum(s ** 2), 1e-300))
+        worst = float(np.max(err / (10 * s + 1e-4 * m + 1e-300)))
+        out[k] = (q, worst)
+    return out
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_rounding_noise_model_covers_emulated_bf16_arithmetic(seed):
+    """The GPU test holds each BF16 tensor to |err|^2 <= 4 |model rms|^2 and each
+    element to 10 model rms (plus an FP32 floor); a NumPy emulation of the
+    BF16 arithmetic (round-to-nearest-even operands at every product, FP32
+    results) meets both, and a model with an eighth of the rounding does not."""
+    p, X, y = _small_net(seed)
+    prob_e, g_e = _emulated_bf16_gradients(p, X, y)
+    res = _noise_check(p, X, y, prob_e, g_e, 2.0 ** -8)
+    for k, (q, worst) in res.items():
+        assert q <= 4.0 and worst <= 1.0, (k, q, worst)
+    assert max(q for q, _ in res.values()) > 0.05      # the model is not vacuous
+    small = _noise_check(p, X, y, prob_e, g_e, 2.0 ** -11)
+    assert max(q for q, _ in small.values()) > 4.0
+
+
+def test_rounding_noise_model_vanishes_without_rounding():
+    p, X, y = _small_net(4)
+    sp, sg = P.rounding_noise_scale(p, X, y, 0.0, 2, 0)
+    assert np.all(sp == 0) and all(np.all(v == 0) for v in sg.values())
