@@ -302,6 +302,22 @@ void cyc_grid_destroy(cyc_grid* g);
  */
 int cyc_scf(const void* d_R, const double* d_alphas, int32_t n_alpha, int64_t lag_min, int32_t n_lag,
             int32_t n_freq, int32_t window, void* d_S, void* stream);
+/*
+ * cyc_scf without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results as cyc_scf (bit for
+ * bit); the weighted lag table lives in a fixed 16 MiB device array that the
+ * library holds on each GPU it runs on until the process ends, so
+ * n_lag * n_alpha <= 2^21 (2097152; larger sizes return CYC_EUNSUPPORTED
+ * before any work is enqueued).  Every call on one GPU shares that array:
+ * calls that overlap on one GPU (different streams, or host threads without
+ * ordering) race and give undefined tables; calls ordered on one stream are
+ * safe.  Nothing in the array needs to start at zero: each call overwrites
+ * the part it reads.  Errors: CYC_EINVAL (as cyc_scf), CYC_EUNSUPPORTED,
+ * CYC_EDEVICE (no current device, symbol lookup or launch failure).
+ */
+int cyc_scf_noalloc(const void* d_R, const double* d_alphas, int32_t n_alpha, int64_t lag_min, int32_t n_lag,
+                    int32_t n_freq, int32_t window, void* d_S, void* stream);
 
 /*
  * Learned cycle-frequency proposal (coarse stage of a coarse-to-fine

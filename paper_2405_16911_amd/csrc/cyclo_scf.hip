@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "../../include/cyclo.h"
 
@@ -72,6 +73,47 @@ __global__ __launch_bounds__(256) void scf_dft_kernel(const float2* P, int A, in
   S[(int64_t)k * A + a] = make_float2(re, im);
 }
 
+// Weighted-table workspace of cyc_scf_noalloc: a fixed device array (each GPU
+// holds its own copy for the life of the process).  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the symbol);
+// it passes the device address that hipGetSymbolAddress returns for the
+// current device.
+constexpr int64_t NOALLOC_MAX = int64_t(1) << 21;  // weighted-table entries (16 MiB)
+static __device__ __align__(256) float2 scratch[NOALLOC_MAX];
+
+constexpr int MAX_DEVICES = 64;
+
+// Device address of `scratch` on the current device, looked up once per device.
+float2* scratch_ptr() {
+  static std::mutex mu;
+  static float2* ptr[MAX_DEVICES] = {};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    ptr[dev] = static_cast<float2*>(p);
+  }
+  return ptr[dev];
+}
+
+bool scf_args_ok(const void* d_R, const double* d_alphas, int32_t n_alpha, int64_t lag_min, int32_t n_lag,
+                 int32_t n_freq, int32_t window, const void* d_S) {
+  return d_R && d_alphas && d_S && n_alpha >= 1 && n_lag >= 1 && n_lag <= MAX_LAGS && n_freq >= 1 &&
+         n_freq <= 65536 && (window == 0 || window == 1) && lag_min >= -(1 << 20) && lag_min <= (1 << 20);
+}
+
+int scf_launch(const void* d_R, const double* d_alphas, int32_t n_alpha, int64_t lag_min, int32_t n_lag,
+               int32_t n_freq, int32_t window, void* d_S, float2* P, hipStream_t st) {
+  const int64_t TA = (int64_t)n_lag * n_alpha;
+  hipLaunchKernelGGL(scf_weight_kernel, dim3((unsigned)((TA + 255) / 256)), dim3(256), 0, st,
+                     reinterpret_cast<const float2*>(d_R), d_alphas, n_alpha, lag_min, n_lag, window, P);
+  hipLaunchKernelGGL(scf_dft_kernel, dim3((unsigned)((n_alpha + 255) / 256), (unsigned)n_freq), dim3(256), 0, st, P,
+                     n_alpha, lag_min, n_lag, n_freq, reinterpret_cast<float2*>(d_S));
+  return hipGetLastError() == hipSuccess ? CYC_OK : CYC_EDEVICE;
+}
+
 }  // namespace scf
 }  // namespace cyclo
 
@@ -81,20 +123,24 @@ extern "C" {
 
 int cyc_scf(const void* d_R, const double* d_alphas, int32_t n_alpha, int64_t lag_min, int32_t n_lag,
             int32_t n_freq, int32_t window, void* d_S, void* stream) {
-  if (!d_R || !d_alphas || !d_S || n_alpha < 1 || n_lag < 1 || n_lag > MAX_LAGS || n_freq < 1 ||
-      n_freq > 65536 || (window != 0 && window != 1) || lag_min < -(1 << 20) || lag_min > (1 << 20))
-    return CYC_EINVAL;
+  if (!scf_args_ok(d_R, d_alphas, n_alpha, lag_min, n_lag, n_freq, window, d_S)) return CYC_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int64_t TA = (int64_t)n_lag * n_alpha;
   float2* P = nullptr;
   if (hipMallocAsync(reinterpret_cast<void**>(&P), sizeof(float2) * TA, st) != hipSuccess) return CYC_ENOMEM;
-  hipLaunchKernelGGL(scf_weight_kernel, dim3((unsigned)((TA + 255) / 256)), dim3(256), 0, st,
-                     reinterpret_cast<const float2*>(d_R), d_alphas, n_alpha, lag_min, n_lag, window, P);
-  hipLaunchKernelGGL(scf_dft_kernel, dim3((unsigned)((n_alpha + 255) / 256), (unsigned)n_freq), dim3(256), 0, st, P,
-                     n_alpha, lag_min, n_lag, n_freq, reinterpret_cast<float2*>(d_S));
-  const bool ok = hipGetLastError() == hipSuccess;
+  const int rc = scf_launch(d_R, d_alphas, n_alpha, lag_min, n_lag, n_freq, window, d_S, P, st);
   (void)hipFreeAsync(P, st);
-  return ok ? CYC_OK : CYC_EDEVICE;
+  return rc;
+}
+
+int cyc_scf_noalloc(const void* d_R, const double* d_alphas, int32_t n_alpha, int64_t lag_min, int32_t n_lag,
+                    int32_t n_freq, int32_t window, void* d_S, void* stream) {
+  if (!scf_args_ok(d_R, d_alphas, n_alpha, lag_min, n_lag, n_freq, window, d_S)) return CYC_EINVAL;
+  if ((int64_t)n_lag * n_alpha > NOALLOC_MAX) return CYC_EUNSUPPORTED;
+  float2* P = scratch_ptr();
+  if (!P) return CYC_EDEVICE;
+  return scf_launch(d_R, d_alphas, n_alpha, lag_min, n_lag, n_freq, window, d_S, P,
+                    reinterpret_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

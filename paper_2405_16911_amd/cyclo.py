@@ -92,6 +92,9 @@ SIGNATURES = {
     "cyc_grid_destroy": (None, [ctypes.c_void_p]),
     "cyc_scf": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                                ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "cyc_scf_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
     "cyc_propose": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -488,8 +491,12 @@ class GridStream:
             pass
 
 
-def cyc_scf(R, alphas, lag_min: int, n_freq: int, window: str = "rect", stream=None):
-    """Cyclic spectrum [n_freq, A] (complex64, GPU) of a complex64 [T, A] lag table R on the GPU."""
+def cyc_scf(R, alphas, lag_min: int, n_freq: int, window: str = "rect", stream=None, noalloc: bool = False,
+            out=None):
+    """Cyclic spectrum [n_freq, A] (complex64, GPU) of a complex64 [T, A] lag table R on the GPU.
+
+    noalloc: call cyc_scf_noalloc (the library allocates nothing; T*A <= 2^21).
+    out: a contiguous complex64 [n_freq, A] CUDA tensor to write (else a new one)."""
     import torch
     if R.dtype != torch.complex64 or not R.is_cuda or not R.is_contiguous() or R.dim() != 2:
         raise ValueError("R must be a contiguous complex64 [T, A] CUDA tensor")
@@ -497,9 +504,15 @@ def cyc_scf(R, alphas, lag_min: int, n_freq: int, window: str = "rect", stream=N
     al = torch.as_tensor(np.asarray(alphas, dtype=np.float64).reshape(-1), device=R.device)
     if al.numel() != A:
         raise ValueError("one cycle frequency per column")
-    S = torch.empty((int(n_freq), A), dtype=torch.complex64, device=R.device)
-    _check(lib().cyc_scf(_p(R), _p(al), A, int(lag_min), T, int(n_freq), {"rect": 0, "hann": 1}[window], _p(S),
-                         _stream_handle(stream)), "cyc_scf")
+    if out is None:
+        S = torch.empty((int(n_freq), A), dtype=torch.complex64, device=R.device)
+    else:
+        S = out
+        if S.dtype != torch.complex64 or not S.is_cuda or not S.is_contiguous() or tuple(S.shape) != (int(n_freq), A):
+            raise ValueError("out must be a contiguous complex64 [n_freq, A] CUDA tensor")
+    name = "cyc_scf_noalloc" if noalloc else "cyc_scf"
+    _check(getattr(lib(), name)(_p(R), _p(al), A, int(lag_min), T, int(n_freq), {"rect": 0, "hann": 1}[window],
+                                _p(S), _stream_handle(stream)), name)
     return S
 
 
