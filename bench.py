@@ -72,18 +72,39 @@ def workload(name: str):
         x = siggen.gmsk_stream(n=32768)
         return dict(x=x, T=32, alphas=np.arange(128) / 128.0, block=32768,
                     desc="gmsk_L32768_T32_A128_push32768")
+    if name == "window_t64":
+        # the learned proposal's dense baseline: one mixed-modulation window of
+        # 65536 samples on the full fine grid (65536 alphas), lags 0..63
+        x = siggen.mixed_stream(5, 0, n=65536)[0]
+        return dict(x=x, T=64, alphas=siggen.uniform_grid(65536, -0.5), block=65536,
+                    desc="mixed_window65536_T64_A65536_push65536")
     raise SystemExit(f"unknown workload {name}")
 
 
-def algorithmic_bytes(wl, q, prof) -> float:
-    """Bytes a contraction launch must move: its samples, the twiddle tables of its
-    alphas (low table [A][KS], high table [A][Kc/KS], complex64) and its FP32 complex
-    chunk partials [2][T][A] per chunk (products per launch from the profiled work)."""
-    import re
+def sample_cells(T: int, A: int):
+    """Cells checked against the oracle's direct sum (features alpha = 0, +-1/4 on
+    the record's grid, the last lag, and seeded random cells)."""
+    rng = np.random.default_rng(2)
+    cells = [(0, A // 2), (1, A // 2), (4, A // 4), (4, 3 * A // 4), (T - 1, A // 2), (T // 2, 0), (3, A // 2 + 1)]
+    cells += [(int(rng.integers(0, T)), int(rng.integers(0, A))) for _ in range(9)]
+    return cells
+
+
+def algorithmic_bytes(wl, prof) -> float:
+    """Bytes the path must move per contraction launch: 8 per sample in and the two
+    complex64 tables (2 T A 8 bytes) per read, over the launches of one step
+    (one reset, every push, one read)."""
+    T, A, L = wl["T"], wl["alphas"].size, wl["x"].size
+    launches_per_step = max(1.0, prof["launches"] / max(1, prof["steps"]))
+    return (8.0 * L + 2.0 * T * A * 8.0) / launches_per_step
+
+
+def design_bytes(wl, q, prof) -> float:
+    """Bytes per launch the design adds: the FP32 chunk partials [2][T][A] written by
+    the contraction (and read back once by the FP64 accumulation)."""
     T, A, Kc = wl["T"], wl["alphas"].size, q["chunk"]
-    KS = int(re.search(r"_k(\d+)", q["kernel_cfg_name"]).group(1))
     prods = prof["work"] / max(1, prof["launches"]) / (T * A)
-    return (prods + T) * 8 + A * (KS + Kc // KS) * 8 + prods / Kc * 2 * T * A * 8
+    return prods / Kc * 2 * T * A * 8
 
 
 def run_gpu(wl, prec: str, split: bool, steps: int, warmup: int, autotune: bool = True):
@@ -115,12 +136,43 @@ def run_gpu(wl, prec: str, split: bool, steps: int, warmup: int, autotune: bool 
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     prof = st.profile_read()
+    prof["steps"] = steps
     st.profile(False)
     q = st.query()
     st.close()
     triples = float(A) * T * n_used
     q["kernel_cfg_name"] = cyclo.cyc_kernel_cfg_info(q["kernel_cfg"])["name"]
-    return dict(sec_per_step=dt, n_used=n_used, triples=triples, prof=prof, query=q, tuned=tuned)
+    cells = sample_cells(T, A)
+    Rh, Rch = R.cpu().numpy(), Rc.cpu().numpy()
+    got = [(complex(Rh[t, j]), complex(Rch[t, j])) for t, j in cells]
+    return dict(sec_per_step=dt, n_used=n_used, triples=triples, prof=prof, query=q, tuned=tuned, cells=got)
+
+
+def oracle_cells(wl):
+    """The oracle's direct sums over the whole record at the sampled cells, and the
+    per-lag scales s_t (for scaled errors).  Part of the CPU (oracle) leg."""
+    from oracle.cyclic import cyclic_cell, scale_per_lag
+    T, alphas, x = wl["T"], wl["alphas"], wl["x"]
+    t0 = time.perf_counter()
+    cells = sample_cells(T, alphas.size)
+    ref = [cyclic_cell(x, alphas[j], t, T) for t, j in cells]
+    s = scale_per_lag(x, T)
+    return dict(cells=cells, ref=ref, s=s, seconds=time.perf_counter() - t0)
+
+
+def error_report(run, oc):
+    """Max / median scaled error |Rhat - R| / s_t over the sampled cells (both tables),
+    and max plain relative error at the feature cells (|R| >= 0.1 s_t)."""
+    scaled, rel = [], []
+    for (t, _), (g, gc), (r, rc) in zip(oc["cells"], run["cells"], oc["ref"]):
+        for a, b in ((g, r), (gc, rc)):
+            e = abs(a - b)
+            scaled.append(e / oc["s"][t])
+            if abs(b) >= 0.1 * oc["s"][t]:
+                rel.append(e / abs(b))
+    return dict(cells=len(scaled), max_scaled_error=float(np.max(scaled)),
+                median_scaled_error=float(np.median(scaled)),
+                feature_cells=len(rel), max_rel_error_at_features=float(np.max(rel)) if rel else None)
 
 
 def cpu_baseline(wl, n_samples: int):
@@ -195,12 +247,22 @@ def run_batch(bw, prec: str, steps: int, warmup: int, compare_single: bool = Fal
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     q = b.query()
+    # one more step with HIP events around every persistent contraction launch
+    # (direct launches instead of the graph while profiling): kernel-only rate
+    b.profile(True)
+    step()
+    kp = b.profile_read()
+    b.profile(False)
     b.close()
     work = float(sum(a.size * T * n for a, n in zip(bw["alists"], nu)))
+    k_tflops = FLOPS_PER_TRIPLE * kp["work"] / (kp["total_ms"] * 1e-3) / 1e12 if kp["total_ms"] > 0 else None
     out = dict(dtype=prec, value=work / dt, ms_per_step=1e3 * dt, work=work,
                kernel_cfg=cyclo.cyc_kernel_cfg_info(q["kernel_cfg"])["name"],
                rounds_per_push=q["rounds"], graph=q["graph"],
-               mfma_frac_whole_path=FLOPS_PER_TRIPLE * work / dt / 1e12 / PEAK_TFLOPS[prec])
+               mfma_frac_whole_path=FLOPS_PER_TRIPLE * work / dt / 1e12 / PEAK_TFLOPS[prec],
+               kernel_ms_per_step=kp["total_ms"], kernel_launches_per_step=kp["launches"],
+               kernel_tflops=k_tflops,
+               kernel_frac=k_tflops / PEAK_TFLOPS[prec] if k_tflops else None)
     if compare_single:
         # the same work as one single-state push per stream, back to back
         old = os.environ.get("CYC_WORKSPACE_MB")
@@ -285,6 +347,10 @@ def run_proposal(n_train: int, pool):
                 speedup=sp["speedup"], miss_rate=ev["trained"]["miss_rate"],
                 fallback_rate=ev["trained"]["fallback_rate"], theta=r["theta"],
                 speedup_no_fallback=sp["speedup_no_fallback"],
+                full_grid_kernel_tflops=sp["full_grid_kernel_tflops"],
+                full_grid_kernel_frac=sp["full_grid_kernel_tflops"] / PEAK_TFLOPS["bf16"],
+                network="4 circular conv1d (64 ch, k 7) + dense 65536->1024 head + a shared local head "
+                        "(64 weights; added to the specified network, see DESIGN reading 17)",
                 miss_rate_no_fallback=ev["trained"]["miss_rate_without_fallback"],
                 miss_rate_untrained=ev["untrained"]["miss_rate_without_fallback"],
                 miss_rate_heuristic=ev["heuristic"]["miss_rate_without_fallback"],
@@ -316,7 +382,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=sorted(PREC_FLAGS), default="f32")
     ap.add_argument("--split", action="store_true")
-    ap.add_argument("--workload", default="qpsk_rrc_2p24")
+    ap.add_argument("--workload", default="qpsk_rrc_2p24",
+                    help="qpsk_rrc_2p24 (default), gmsk_32k, window_t64, or none (extra forms only)")
     ap.add_argument("--variants", default="bf16,f16,bf16s,f16s",
                     help="extra precision forms timed after the main one ('' for none)")
     ap.add_argument("--cpu-samples", type=int, default=6 << 20)
@@ -328,6 +395,8 @@ def main():
     ap.add_argument("--proposal-train", type=int, default=49152,
                     help="training windows of the learned proposal trained inside the run")
     ap.add_argument("--batch-streams", type=int, default=512)
+    ap.add_argument("--batch-precisions", default="bf16",
+                    help="precisions of the batch runs with --workload none (comma-separated)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain elementwise copy of 256 MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -345,6 +414,15 @@ def main():
         from multiprocessing import Pool
         # window generators, forked before anything in this process touches the GPU
         pool = Pool(max(1, min(16, os.cpu_count() or 1)))
+    forms = {}
+    if args.workload == "none":
+        # forms only (for profiling one form at a time); not the measurement line
+        if "batch" in forms_wanted:
+            bw = batch_workload(args.batch_streams)
+            forms["batch"] = dict(workload=bw["desc"], runs=[run_batch(bw, p, max(1, args.steps), args.warmup)
+                                                             for p in args.batch_precisions.split(",")])
+        print(json.dumps({"forms": forms}), flush=True)
+        return
     wl = workload(args.workload)
     main_run = run_gpu(wl, args.precision, args.split, args.steps, args.warmup, not args.no_autotune)
     prof = main_run["prof"]
@@ -353,18 +431,22 @@ def main():
     peak = PEAK_TFLOPS[args.precision]
     value = main_run["triples"] / main_run["sec_per_step"]
 
-    variants = []
+    variants, variant_runs = [], []
     for v in [s for s in args.variants.split(",") if s]:
         prec, split = v.rstrip("s"), v.endswith("s")
         if prec == args.precision and split == args.split:
             continue
         r = run_gpu(wl, prec, split, max(2, args.steps), 1, not args.no_autotune)
         p = r["prof"]
+        variant_runs.append(r)
         variants.append(dict(dtype=prec, split=split, value=r["triples"] / r["sec_per_step"],
                              kernel_cfg=r["query"]["kernel_cfg_name"],
                              ms_per_step=1e3 * r["sec_per_step"],
+                             speedup_vs_main=(r["triples"] / r["sec_per_step"]) / value,
                              kernel_tflops=FLOPS_PER_TRIPLE * p["work"] / (p["total_ms"] * 1e-3) / 1e12,
                              kernel_frac=(FLOPS_PER_TRIPLE * p["work"] / (p["total_ms"] * 1e-3) / 1e12)
+                             / PEAK_TFLOPS[prec],
+                             whole_path_frac=FLOPS_PER_TRIPLE * r["triples"] / r["sec_per_step"] / 1e12
                              / PEAK_TFLOPS[prec]))
 
     out = {
@@ -382,13 +464,16 @@ def main():
                      "traffic": (profiled_traffic(main_run["query"]["kernel_cfg_name"])
                                  if args.workload == "qpsk_rrc_2p24" else None),
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 counters scaled by a copy kernel)",
-                     "algorithmic_bytes_per_launch": algorithmic_bytes(wl, main_run["query"], prof),
+                     "algorithmic_bytes_per_launch": algorithmic_bytes(wl, prof),
+                     "design_bytes_per_launch": design_bytes(wl, main_run["query"], prof),
+                     "design_bytes_note": "FP32 chunk partials written by the contraction and read once by "
+                                          "the FP64 accumulation; not algorithmic",
                      "kernel": "contract (chunk contraction)", "kernel_ms_avg": kernel_ms,
                      "launches": prof["launches"], "flops_per_launch": FLOPS_PER_TRIPLE * prof["work"]
                      / max(1, prof["launches"])},
+        "whole_path_frac": FLOPS_PER_TRIPLE * value / 1e12 / peak,
         "variants": variants,
     }
-    forms = {}
     if "batch" in forms_wanted:
         bw = batch_workload(args.batch_streams)
         forms["batch"] = dict(workload=bw["desc"], n_streams=len(bw["xs"]),
@@ -406,6 +491,13 @@ def main():
         out["forms"] = forms
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_samples)
+        # the same (oracle) leg: direct sums at sampled cells for the error of every precision
+        oc = oracle_cells(wl)
+        out["error_vs_oracle"] = dict(main=error_report(main_run, oc), oracle_seconds=oc["seconds"],
+                                      cells="features alpha = 0, +-1/4 and seeded random cells, both tables, "
+                                            "direct FP64 sums over the whole record")
+        for v, r in zip(variants, variant_runs):
+            v["error_vs_oracle"] = error_report(r, oc)
     print(json.dumps(out), flush=True)
 
 

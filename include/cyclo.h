@@ -249,6 +249,14 @@ void cyc_batch_destroy(cyc_batch* b);
 /* Kernel configuration in use, number of rounds of the last push and whether
  * the last push replayed a captured graph (outputs may be NULL). */
 int cyc_batch_query(const cyc_batch* b, int32_t* kernel_cfg, int32_t* rounds, int32_t* graph);
+/* Timing of the batch's persistent contraction launches, as cyc_profile /
+ * cyc_profile_read for one state: while enabled, pushes launch directly
+ * instead of through the graph, and HIP events bracket every contraction
+ * launch (push rounds and the partial chunks of a read) on the call's stream;
+ * work = products x lags x cycle frequencies contracted.  Enabling clears
+ * the record. */
+int cyc_batch_profile(cyc_batch* b, int32_t enable);
+int cyc_batch_profile_read(cyc_batch* b, double* total_ms, int64_t* launches, double* work);
 
 /*
  * Uniform-grid form: the same tables R, Rc (definition and conventions as
@@ -320,6 +328,57 @@ int cyc_scf_noalloc(const void* d_R, const double* d_alphas, int32_t n_alpha, in
                     int32_t n_freq, int32_t window, void* d_S, void* stream);
 
 /*
+ * Cycle-frequency estimation (the paper leaves it for future work, Sec. 6;
+ * Sec. 1 describes coarse-to-fine searches among related estimators), on one
+ * table of the uniform grid alpha_k = alpha0 + k / n_alpha:
+ *  1. noise scale sigma[t][c] per lag t and block c of 64 bins: the median of
+ *     |R[t][.]| over blocks c-1, c, c+1 (circular) / sqrt(2 ln 2);
+ *  2. q[k] = max_t |R[t][k]| / sigma[t][k / 64];
+ *  3. candidates: q[k] > kappa, q[k] > q[k-1] and q[k] >= q[k+1] (circular);
+ *  4. leakage masking in descending q (ties -> lower k): a candidate is kept
+ *     if at some lag it exceeds kappa sigma and
+ *     |R[t][k]| > (pi/2) n_alpha / (n_used (d - 1/2)) |R[t][p]| for every kept
+ *     p at circular distance d: twice the most a feature within half a bin
+ *     of p leaks there through the Dirichlet kernel of n_used products, which
+ *     needs a grid at least as fine as 1/n_used (n_used <= n_alpha);
+ *  5. (cyc_estimate_cycle_freqs) refinement on the zoom grid
+ *     alpha_k + (j - zoom) / (zoom n_alpha), j = 0 .. 2 zoom: the first zoom
+ *     point with the largest max_t |R| / sigma[t][k / 64].
+ * |R| = sqrt(Re^2 + Im^2), scales and comparisons are FP64.
+ *
+ * cyc_cfe_detect: steps 1-4 on a device table d_R, complex64
+ *   [n_lag][n_alpha] (n_alpha a multiple of 64, 1 <= n_lag <= 4096,
+ *   1 <= n_used <= n_alpha, kappa >= 0 finite).  exclude_bin (-1 for none)
+ *   takes part in the masking but is never reported (the alpha = 0 bin of the
+ *   non-conjugate table).  Writes the kept bins in ascending order to d_bins
+ *   (int32, the first min(count, max_out)), their number to *d_count (device
+ *   int32) and the scales to d_sigma (FP64 [n_lag][n_alpha / 64], device).
+ *   Synchronises the stream.  More than 4096 candidates: CYC_EUNSUPPORTED.
+ * cyc_cfe_refine: step 5 on a device zoom table d_Rz, complex64
+ *   [n_lag][n_peaks (2 zoom + 1)] (peak p's columns contiguous), with the
+ *   detections d_bins and scales d_sigma of cyc_cfe_detect (n_alpha the
+ *   coarse grid size): d_j[p] = best zoom index, d_q[p] = its statistic.
+ * cyc_estimate_cycle_freqs: the whole estimator from n complex64 samples at
+ *   d_x (device): the coarse table (table 0 = R, 1 = Rc) from the exact
+ *   uniform-grid form when n_alpha is a power of two <= 65536, else the dense
+ *   FP32 contraction; cyc_cfe_detect (exclude_zero: skip the alpha = 0 bin of
+ *   R); the zoom table by the dense FP32 contraction; cyc_cfe_refine.  Host
+ *   outputs: *count (all detections) and, for the first min(count, max_out)
+ *   in ascending bin order, bins, alpha_hat (cycles/sample) and stat (the
+ *   refined q).  Allocates its own work space; synchronises the stream.
+ * Errors: CYC_EINVAL (NULL, sizes, n_used > n_alpha, non-finite arguments),
+ * CYC_EUNSUPPORTED (too many candidates), CYC_ENOMEM, CYC_EDEVICE.
+ */
+int cyc_cfe_detect(const void* d_R, int32_t n_lag, int32_t n_alpha, int64_t n_used, double kappa,
+                   int32_t exclude_bin, int32_t max_out, int32_t* d_bins, int32_t* d_count, double* d_sigma,
+                   void* stream);
+int cyc_cfe_refine(const void* d_Rz, int32_t n_lag, int32_t n_peaks, int32_t zoom, const int32_t* d_bins,
+                   const double* d_sigma, int32_t n_alpha, int32_t* d_j, double* d_q, void* stream);
+int cyc_estimate_cycle_freqs(const void* d_x, int64_t n, double alpha0, int32_t n_alpha, int32_t n_lag,
+                             int32_t table, double kappa, int32_t zoom, int32_t exclude_zero, int32_t max_out,
+                             double* alpha_hat, double* stat, int32_t* bins, int32_t* count, void* stream);
+
+/*
  * Learned cycle-frequency proposal (coarse stage of a coarse-to-fine
  * estimator; the paper's related work in Sec. 1 describes the two-stage idea
  * and Sec. 6 names cycle-frequency estimation as future work).
@@ -365,7 +424,8 @@ int cyc_model_train_step(cyc_model* m, const float* d_feat, const float* d_label
  * lower index), each widened by +-width bins circularly, plus zero_bin (-1 for
  * none) -> d_sel [n][1024] (1 = evaluate), and d_conf [n] = 1 - the largest
  * probability outside the selection (fall back to the full grid below a
- * threshold).
+ * threshold).  NaN probabilities are never selected, and a window with a NaN
+ * or infinite probability gets d_conf = 0.
  */
 int cyc_select(const float* d_prob, int32_t n, int32_t topk, int32_t width, int32_t zero_bin,
                uint8_t* d_sel, float* d_conf, void* stream);
@@ -377,7 +437,9 @@ int cyc_select(const float* d_prob, int32_t n, int32_t topk, int32_t width, int3
  *              order, -1 after the last; coarse bin k holds the fine cycle
  *              frequencies -1/2 + (64 k + f)/65536, f = 0..63;
  *   d_n_bins   int32 [n_windows]: the number of selected bins;
- *   d_conf     float [n_windows]: 1 - the largest probability left out;
+ *   d_conf     float [n_windows]: 1 - the largest probability left out (0 when
+ *              a probability or a feature of the window is NaN or infinite,
+ *              e.g. after a non-finite sample, so that the window falls back);
  *   d_fallback uint8 [n_windows]: 1 when conf < theta (evaluate the full grid).
  * The exact estimator then runs on those cycle frequencies (cyc_create or
  * cyc_batch_create).  Uses the model's own scratch buffers: calls on one model

@@ -37,7 +37,7 @@ lobe (spacing 1/A <= 1/N_used, as the grid of the Full mode in Sec. 4 is):
    and alpha_hat = the zoom point with the largest max_t |R| / sigma[t, k div B]
    (the detection's coarse scale; ties -> lower j).  Resolution 1 / (Z A).
 
-Magnitudes, scales and every comparison are FP64.
+Magnitudes sqrt(Re^2 + Im^2), scales and every comparison are FP64.
 """
 from __future__ import annotations
 
@@ -50,15 +50,21 @@ BLOCK = 64
 HALF_PI = np.pi / 2.0
 
 
+def magnitudes(R) -> np.ndarray:
+    """|R| = sqrt(Re^2 + Im^2) in FP64 (one rounding of the sum, then the square root)."""
+    R = np.asarray(R).astype(np.complex128)
+    return np.sqrt(R.real * R.real + R.imag * R.imag)
+
+
 def scales(R) -> np.ndarray:
     """sigma[t, c] for the blocks of B bins of a [T, A] table."""
-    m = np.abs(np.asarray(R).astype(np.complex128))
+    m = magnitudes(R)
     return local_sigma(m, m.shape[1] // BLOCK)
 
 
 def ratios(R, sigma) -> np.ndarray:
     """|R[t, k]| / sigma[t, k div B] (inf where sigma is 0 and |R| > 0, 0 for 0/0)."""
-    m = np.abs(np.asarray(R).astype(np.complex128))
+    m = magnitudes(R)
     s = np.repeat(sigma, BLOCK, axis=1)
     with np.errstate(divide="ignore", invalid="ignore"):
         q = m / s
@@ -86,7 +92,7 @@ def leak_factor(d: int, A: int, N: int) -> float:
 
 def detect(R, kappa: float, N: int, exclude: int | None = None):
     """Detected bins of a table, ascending, and the scales sigma."""
-    m = np.abs(np.asarray(R).astype(np.complex128))
+    m = magnitudes(R)
     A = m.shape[1]
     sigma = scales(R)
     r = ratios(R, sigma)
@@ -128,7 +134,7 @@ def zoom_grid(alpha_k: float, A: int, Z: int) -> np.ndarray:
 def refine(Rz, sigma_col):
     """(j, q_j): the zoom column with the largest max_t |R[t, j]| / sigma_col[t]
     (ties -> lower j)."""
-    m = np.abs(np.asarray(Rz).astype(np.complex128))
+    m = magnitudes(Rz)
     with np.errstate(divide="ignore", invalid="ignore"):
         r = m / sigma_col[:, None]
     q = np.where(np.isnan(r), 0.0, r).max(axis=0)

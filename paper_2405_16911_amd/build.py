@@ -15,7 +15,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcyclo.so")
-SOURCES = ["cyclo_kernels.hip", "cyclo_runtime.hip", "cyclo_batch.hip", "cyclo_nn.hip", "cyclo_grid.hip", "cyclo_scf.hip", "cyclo_window.hip"]
+SOURCES = ["cyclo_kernels.hip", "cyclo_runtime.hip", "cyclo_batch.hip", "cyclo_nn.hip", "cyclo_grid.hip", "cyclo_scf.hip", "cyclo_window.hip", "cyclo_cfe.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -75,6 +75,11 @@ struct cyc_batch {
   int grid = 0;
   int rounds = 0, graphed = 0;
   bool poisoned = false;
+  // profiling: HIP events around every persistent contraction launch
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  double prof_work = 0.0;
 
   float2* pend_buf(int s, int which) const { return pend + ((int64_t)s * 2 + which) * PC; }
   BCounts* d_cnt() const { return reinterpret_cast<BCounts*>(meta + lay.cnt); }
@@ -91,6 +96,7 @@ namespace {
 
 void batch_free(cyc_batch* b) {
   if (!b) return;
+  for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);
@@ -195,13 +201,37 @@ BatchArgs batch_args(cyc_batch* b) {
 }
 
 // Enqueues the push pipeline of one round on st.
-hipError_t enqueue_push(cyc_batch* b, hipStream_t st) {
+// The persistent contraction launch, bracketed by HIP events while profiling
+// (work = the round's products times lags times cycle frequencies).
+hipError_t contract_launch(cyc_batch* b, double work, hipStream_t st) {
   int ncfg = 0;
   const KernelCfg& cfg = kernel_cfgs(&ncfg)[b->cfg];
+  if (!b->prof) return cfg.blaunch(batch_args(b), b->grid, st);
+  while (b->ev.size() < b->ev_used + 2) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return hipErrorOutOfMemory;
+    b->ev.push_back(e);
+  }
+  hipEvent_t e0 = b->ev[b->ev_used], e1 = b->ev[b->ev_used + 1];
+  b->ev_used += 2;
+  b->prof_work += work;
+  hipError_t e = hipEventRecord(e0, st);
+  if (e == hipSuccess) e = cfg.blaunch(batch_args(b), b->grid, st);
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  return e;
+}
+
+double round_work(const cyc_batch* b, const std::vector<BJob>& jobs) {
+  double w = 0.0;
+  for (const BJob& j : jobs) w += (double)j.n_prod * j.A * b->T;
+  return w;
+}
+
+hipError_t enqueue_push(cyc_batch* b, hipStream_t st, double work = 0.0) {
   hipError_t e = launch_batch_small(b->d_jobs(), b->d_cnt(), b->d_acc(), b->d_acc_tiles(),
                                     b->d_copy(), b->d_copy_tiles(), &b->d_cnt()->counter, 0, st);
   if (e != hipSuccess) return e;
-  e = cfg.blaunch(batch_args(b), b->grid, st);
+  e = contract_launch(b, work, st);
   if (e != hipSuccess) return e;
   return launch_batch_small(b->d_jobs(), b->d_cnt(), b->d_acc(), b->d_acc_tiles(), b->d_copy(),
                             b->d_copy_tiles(), &b->d_cnt()->counter, 1, st);
@@ -235,8 +265,12 @@ void ensure_graph(cyc_batch* b) {
 hipError_t run_round(cyc_batch* b, const Round& r, hipStream_t st) {
   hipError_t e = upload(b, r, st);
   if (e != hipSuccess) return e;
-  ensure_graph(b);
   ++b->rounds;
+  if (b->prof) {  // direct launches, so that the contraction can be timed
+    b->graphed = 0;
+    return enqueue_push(b, st, round_work(b, r.jobs));
+  }
+  ensure_graph(b);
   if (b->exec) {
     b->graphed = 1;
     return hipGraphLaunch(b->exec, st);
@@ -532,7 +566,7 @@ int cyc_batch_read(cyc_batch* b, void* const* d_R, void* const* d_Rc, int64_t* n
     if (e == hipSuccess)
       e = launch_batch_small(b->d_jobs(), b->d_cnt(), b->d_acc(), b->d_acc_tiles(), b->d_copy(),
                              b->d_copy_tiles(), &b->d_cnt()->counter, 0, st);
-    if (e == hipSuccess && !r.jobs.empty()) e = cfg.blaunch(batch_args(b), b->grid, st);
+    if (e == hipSuccess && !r.jobs.empty()) e = contract_launch(b, round_work(b, r.jobs), st);
     if (e == hipSuccess) e = launch_batch_finalize(b->d_jobs(), b->d_fin(), b->d_acc_tiles(), b->d_cnt(), st);
     r.clear();
     return e;
@@ -607,6 +641,32 @@ void cyc_batch_destroy(cyc_batch* b) {
   if (!b) return;
   (void)hipDeviceSynchronize();
   batch_free(b);
+}
+
+int cyc_batch_profile(cyc_batch* b, int32_t enable) {
+  if (!b) return CYC_EINVAL;
+  b->prof = enable != 0;
+  if (b->prof) {
+    b->ev_used = 0;
+    b->prof_work = 0.0;
+  }
+  return CYC_OK;
+}
+
+int cyc_batch_profile_read(cyc_batch* b, double* total_ms, int64_t* launches, double* work) {
+  if (!b) return CYC_EINVAL;
+  double ms = 0.0;
+  for (size_t i = 0; i + 1 < b->ev_used; i += 2) {
+    float t = 0.f;
+    if (hipEventSynchronize(b->ev[i + 1]) != hipSuccess ||
+        hipEventElapsedTime(&t, b->ev[i], b->ev[i + 1]) != hipSuccess)
+      return CYC_EDEVICE;
+    ms += t;
+  }
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = (int64_t)(b->ev_used / 2);
+  if (work) *work = b->prof_work;
+  return CYC_OK;
 }
 
 int cyc_batch_query(const cyc_batch* b, int32_t* kernel_cfg, int32_t* rounds, int32_t* graph) {

@@ -611,9 +611,11 @@ __global__ void coarse_label_kernel(const float2* R, const float2* Rc, int T, in
 
 // Per window: top-k bins of prob (ties -> lower index; NaN bins are never
 // chosen), widened by +-width circularly, plus zero_bin; conf = 1 - max prob
-// outside the selection, or 0 when any probability is NaN or infinite.
+// outside the selection, or 0 when any probability is NaN or infinite, or
+// (feat given, [3][n][LEN]) any of the window's features is.
 __global__ __launch_bounds__(256) void select_kernel(const float* prob, int n, int topk, int width,
-                                                     int zero_bin, uint8_t* sel, float* conf) {
+                                                     int zero_bin, uint8_t* sel, float* conf,
+                                                     const float* feat) {
   __shared__ float p[NOUT];
   __shared__ uint8_t chosen[NOUT], s8[NOUT];
   __shared__ float rv[256];
@@ -663,6 +665,9 @@ __global__ __launch_bounds__(256) void select_kernel(const float* prob, int n, i
     if (!s8[i]) mx = fmaxf(mx, p[i]);
     if (!(fabsf(p[i]) <= 3.402823466e38f)) bad = 1;  // NaN or infinite
   }
+  if (feat)
+    for (int i = tid; i < 3 * NOUT; i += 256)
+      if (!(fabsf(feat[((int64_t)(i / NOUT) * n + w) * NOUT + i % NOUT]) <= 3.402823466e38f)) bad = 1;
   rv[tid] = mx;
   bad = __syncthreads_or(bad);
   for (int k = 128; k > 0; k >>= 1) {
@@ -989,7 +994,8 @@ int cyc_select(const float* d_prob, int32_t n, int32_t topk, int32_t width, int3
       zero_bin < -1 || zero_bin >= NOUT)
     return CYC_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(select_kernel, dim3(n), dim3(256), 0, st, d_prob, n, topk, width, zero_bin, d_sel, d_conf);
+  hipLaunchKernelGGL(select_kernel, dim3(n), dim3(256), 0, st, d_prob, n, topk, width, zero_bin, d_sel, d_conf,
+                     (const float*)nullptr);
   return hipGetLastError() == hipSuccess ? CYC_OK : CYC_EDEVICE;
 }
 
@@ -1007,7 +1013,10 @@ int cyc_propose(cyc_model* m, const void* d_x, int32_t n_windows, int32_t topk, 
   const int64_t nz = (int64_t)n * NOUT;
   hipLaunchKernelGGL(head_out_kernel, dim3(nb(nz)), dim3(256), 0, st, m->z, m->w + m->offbh, m->pprob,
                      (const float*)nullptr, (float*)nullptr, 0.f, (double*)nullptr, nz);
-  hipLaunchKernelGGL(select_kernel, dim3(n), dim3(256), 0, st, m->pprob, n, topk, width, zero_bin, m->psel, d_conf);
+  // a window with a non-finite feature (a NaN or infinite sample) falls back too:
+  // the network's ReLUs would otherwise turn NaN into finite outputs
+  hipLaunchKernelGGL(select_kernel, dim3(n), dim3(256), 0, st, m->pprob, n, topk, width, zero_bin, m->psel, d_conf,
+                     (const float*)m->pfeat);
   hipLaunchKernelGGL(compact_bins_kernel, dim3(n), dim3(256), 0, st, m->psel, d_conf, theta, d_bins, d_n_bins,
                      d_fallback);
   return hipGetLastError() == hipSuccess ? CYC_OK : CYC_EDEVICE;

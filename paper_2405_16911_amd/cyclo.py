@@ -61,6 +61,9 @@ SIGNATURES = {
     "cyc_batch_destroy": (None, [ctypes.c_void_p]),
     "cyc_batch_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "cyc_batch_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "cyc_batch_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
     "cyc_model_num_params": (ctypes.c_int64, []),
     "cyc_model_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_uint32,
                                         ctypes.c_void_p]),
@@ -95,6 +98,16 @@ SIGNATURES = {
     "cyc_scf_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                        ctypes.c_void_p]),
+    "cyc_cfe_detect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                      ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cyc_cfe_refine": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "cyc_estimate_cycle_freqs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
+                                                ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                                ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cyc_propose": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -410,6 +423,15 @@ class CyclicBatch:
     def query(self) -> dict:
         return cyc_batch_query(self._b)
 
+    def profile(self, enable: bool):
+        _check(lib().cyc_batch_profile(self._b, 1 if enable else 0), "cyc_batch_profile")
+
+    def profile_read(self) -> dict:
+        ms, n, w = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib().cyc_batch_profile_read(self._b, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(w)),
+               "cyc_batch_profile_read")
+        return dict(total_ms=ms.value, launches=n.value, work=w.value)
+
     def close(self):
         if self._b is not None:
             cyc_batch_destroy(self._b)
@@ -514,6 +536,43 @@ def cyc_scf(R, alphas, lag_min: int, n_freq: int, window: str = "rect", stream=N
     _check(getattr(lib(), name)(_p(R), _p(al), A, int(lag_min), T, int(n_freq), {"rect": 0, "hann": 1}[window],
                                 _p(S), _stream_handle(stream)), name)
     return S
+
+
+# ----------------------------------------------------------------------------- cycle-frequency estimation
+
+def cyc_cfe_detect(R, n_used: int, kappa: float = 7.0, exclude_bin: int = -1, max_out: int = 1024, stream=None):
+    """Detections on a complex64 [T, A] CUDA table: (bins int32 array ascending, sigma [T, A/64] FP64 tensor)."""
+    import torch
+    if R.dtype != torch.complex64 or not R.is_cuda or not R.is_contiguous() or R.dim() != 2:
+        raise ValueError("R must be a contiguous complex64 [T, A] CUDA tensor")
+    T, A = R.shape
+    bins = torch.empty(max(int(max_out), 1), dtype=torch.int32, device=R.device)
+    cnt = torch.zeros(1, dtype=torch.int32, device=R.device)
+    sigma = torch.empty((T, A // 64), dtype=torch.float64, device=R.device)
+    _check(lib().cyc_cfe_detect(_p(R), T, A, int(n_used), float(kappa), int(exclude_bin), int(max_out), _p(bins),
+                                _p(cnt), _p(sigma), _stream_handle(stream)), "cyc_cfe_detect")
+    n = int(cnt.item())
+    return bins[:min(n, int(max_out))].cpu().numpy(), sigma, n
+
+
+def cyc_estimate_cycle_freqs(x, alpha0: float, n_alpha: int, n_lag: int, table: str = "R", kappa: float = 7.0,
+                             zoom: int = 16, exclude_zero: bool = True, max_out: int = 1024, stream=None):
+    """Cycle-frequency estimates from a 1-D complex64 CUDA tensor of samples: a list of
+    (coarse bin, alpha_hat, statistic), ascending in bin, and the total detection count."""
+    import torch
+    if x.dtype != torch.complex64 or not x.is_cuda or not x.is_contiguous() or x.dim() != 1:
+        raise ValueError("x must be a contiguous 1-D complex64 CUDA tensor")
+    ah = np.zeros(max(int(max_out), 1), dtype=np.float64)
+    st = np.zeros_like(ah)
+    bn = np.zeros(max(int(max_out), 1), dtype=np.int32)
+    cnt = ctypes.c_int32(0)
+    _check(lib().cyc_estimate_cycle_freqs(_p(x), int(x.numel()), float(alpha0), int(n_alpha), int(n_lag),
+                                          {"R": 0, "Rc": 1}[table], float(kappa), int(zoom), 1 if exclude_zero else 0,
+                                          int(max_out), ah.ctypes.data_as(ctypes.c_void_p),
+                                          st.ctypes.data_as(ctypes.c_void_p), bn.ctypes.data_as(ctypes.c_void_p),
+                                          ctypes.byref(cnt), _stream_handle(stream)), "cyc_estimate_cycle_freqs")
+    n = min(cnt.value, int(max_out))
+    return [(int(bn[i]), float(ah[i]), float(st[i])) for i in range(n)], cnt.value
 
 
 # ----------------------------------------------------------------------------- learned proposal

@@ -374,6 +374,14 @@ def speed(model, xt, fg: FullGrid, theta: float, conf_curve=None, fft: FullGrid 
         fg.tables(xt[i])
     torch.cuda.synchronize()
     t_full = time.perf_counter() - t
+    # kernel-only rate of the dense full grid: HIP events around its contraction
+    # launches over a few more windows
+    fg.st.profile(True)
+    for i in range(min(n, 16)):
+        fg.tables(xt[i])
+    kp = fg.st.profile_read()
+    fg.st.profile(False)
+    k_tflops = 16.0 * kp["work"] / (kp["total_ms"] * 1e-3) / 1e12 if kp["total_ms"] > 0 else None
     t_fft = None
     if fft is not None:
         t = time.perf_counter()
@@ -421,7 +429,7 @@ def speed(model, xt, fg: FullGrid, theta: float, conf_curve=None, fft: FullGrid 
                speedup=t_full / (t_front + t_path), speedup_no_fallback=t_full / (t_front + t_sel),
                evaluated_alphas_per_window=float(sel_h.sum(1).mean() * PER),
                ideal_speedup_no_fallback=float(FINE / (sel_h.sum(1).mean() * PER)),
-               max_rel_diff_vs_full_grid=diff)
+               max_rel_diff_vs_full_grid=diff, full_grid_kernel_tflops=k_tflops)
     if conf_curve is not None:
         res["predicted_speedup"] = [float(t_full / (t_front + (1 - f) * t_sel + f * t_full)) for f in conf_curve]
     return res
