@@ -61,6 +61,15 @@ extern "C" {
 #define CYC_TW_SPLIT  0x4u
 /* cyc_read writes complex128 tables instead of complex64. */
 #define CYC_OUT_C128  0x8u
+/* Which tables a state keeps (the `conj` attribute of the paper's block,
+ * Sec. 4, selects the conjugate form): CYC_TBL_R only the non-conjugate
+ * table, CYC_TBL_RCONJ only the conjugate one, neither or both flags both.
+ * A one-table state contracts only that table (half the matrix-core work;
+ * its table is bitwise the one a two-table state gives), and cyc_read
+ * returns CYC_EINVAL when asked for the other table.  cyc_create and
+ * cyc_create2 only (window states and batches: CYC_EUNSUPPORTED). */
+#define CYC_TBL_R     0x10u
+#define CYC_TBL_RCONJ 0x20u
 
 typedef struct cyc_state cyc_state;
 
@@ -70,7 +79,7 @@ typedef struct cyc_state cyc_state;
  *   alphas_host : host array of n_alpha FP64 cycle frequencies (copied).
  *   n_alpha     : number of cycle frequencies, >= 1.
  *   n_lag       : T, the number of lags 0..T-1, 1 <= T <= 4096.
- *   flags       : CYC_OP_* | CYC_TW_SPLIT | CYC_OUT_C128.
+ *   flags       : CYC_OP_* | CYC_TW_SPLIT | CYC_OUT_C128 | CYC_TBL_R | CYC_TBL_RCONJ.
  *   stream      : stream for the set-up work; the call returns after it ends.
  * Errors: CYC_EINVAL (NULL pointer, n_alpha < 1, n_lag out of range,
  * non-finite alpha, unknown flag bits), CYC_EUNSUPPORTED (CYC_TW_SPLIT with

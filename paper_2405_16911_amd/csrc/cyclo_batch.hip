@@ -308,6 +308,7 @@ int cyc_batch_create(cyc_batch** out, int32_t n_streams, const int64_t* alpha_of
                      const double* alphas, int32_t n_lag, uint32_t flags, void* stream) {
   if (!out || n_streams < 1 || !alpha_offsets || !alphas || n_lag < 1 || n_lag > 4096)
     return CYC_EINVAL;
+  if (flags & (CYC_TBL_R | CYC_TBL_RCONJ)) return CYC_EUNSUPPORTED;  // batches keep both tables
   if (flags & ~(CYC_OP_MASK | CYC_TW_SPLIT | CYC_OUT_C128)) return CYC_EINVAL;
   const int prec = (int)(flags & CYC_OP_MASK);
   if (prec == 3) return CYC_EINVAL;

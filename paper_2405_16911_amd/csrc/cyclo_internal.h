@@ -103,6 +103,9 @@ struct KernelCfg {
   // persistent batched form (nullptr if none) and its resident grid size
   BatchLaunch blaunch;
   int (*bgrid)();
+  // tables computed: 0 both (tile columns: aw cycle frequencies of R then of
+  // Rc), 1 R only or 2 Rc only (tile columns: 2 aw cycle frequencies)
+  int tbl;
 };
 
 const KernelCfg* kernel_cfgs(int* n);
@@ -119,7 +122,7 @@ hipError_t launch_tables(const double* alpha_r, int A, int ks, int nsteps, float
 hipError_t launch_phase(const double* alpha_r, int A, int64_t base0, int Kc, int nc,
                         double2* E, hipStream_t st);
 hipError_t launch_accumulate(double2* S, const float2* part, const double2* E, int T, int A,
-                             int nc, int first, hipStream_t st);
+                             int nc, int first, int tbl, hipStream_t st);
 hipError_t launch_finalize(const double2* S, int hasS, const float2* part0, const double2* E0,
                            int hasP, int T, int A, int64_t n_used, void* R, void* Rc, int c128,
                            hipStream_t st);

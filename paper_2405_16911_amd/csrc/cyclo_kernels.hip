@@ -235,7 +235,7 @@ struct Tile {
 // A lane holds A'[row = lane%32][k = lane/32] and B'[k = lane/32][col = lane%32].
 // Hankel value for row (t, cr) and component c: component (cr ^ c) of
 // x[s0+l+t], negated for cr = 0, c = 1.
-template <int TW, int AW, int WAVES_M, int WAVES_N, int KS>
+template <int TW, int AW, int WAVES_M, int WAVES_N, int KS, int TBL>
 __device__ __forceinline__ void contract_f32_tile(const ContractArgs& a, TileId tid_in) {
   constexpr int NT = 64 * WAVES_M * WAVES_N;
   constexpr int MR = 2 * TW, NC = 2 * AW;
@@ -255,7 +255,7 @@ __device__ __forceinline__ void contract_f32_tile(const ContractArgs& a, TileId 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
   const int h = lane >> 5, l32 = lane & 31;
-  const Tile tl(a, tid_in, TW, AW, KS);
+  const Tile tl(a, tid_in, TW, TBL ? 2 * AW : AW, KS);
   const int ns = tl.ns;
 
   const int ga = tid % AW, gj = (tid / AW) * G;
@@ -267,6 +267,15 @@ __device__ __forceinline__ void contract_f32_tile(const ContractArgs& a, TileId 
     lo[g] = aval ? a.Lo[(int64_t)galpha * KS + gj + g] : make_float2(0.f, 0.f);
   const float2* Hrow = a.H + (int64_t)(aval ? galpha : 0) * tl.nsteps;
   auto hptr = [&](int ks) { return Hrow + min(ks, tl.nsteps - 1); };
+  // one table: the thread's second cycle frequency (tile column AW + ga)
+  const int galpha2 = galpha + AW;
+  const bool aval2 = TBL && galpha2 < a.A;
+  float2 lo2[TBL ? G : 1];
+#pragma unroll
+  for (int g = 0; g < (TBL ? G : 1); ++g)
+    lo2[g] = aval2 ? a.Lo[(int64_t)galpha2 * KS + gj + g] : make_float2(0.f, 0.f);
+  const float2* Hrow2 = a.H + (int64_t)(aval2 ? galpha2 : 0) * tl.nsteps;
+  auto hptr2 = [&](int ks) { return TBL ? Hrow2 + min(ks, tl.nsteps - 1) : (const float2*)nullptr; };
 
   int xoff[WM];
   uint32_t xneg[WM];
@@ -278,9 +287,17 @@ __device__ __forceinline__ void contract_f32_tile(const ContractArgs& a, TileId 
     xneg[rb] = (cr == 0 && h == 1) ? 0x80000000u : 0u;
   }
 
-  auto produce = [&](int buf, float2 hv) {
+  auto produce = [&](int buf, float2 hv, float2 hv2) {
     float2 y[G], yc[G];
-    modulate<G>(&Xy[buf][gj], hv, lo, y, yc);
+    if (TBL) {
+      float2 lo2g[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) lo2g[g] = lo2[TBL ? g : 0];
+      modulate1<G, TBL - 1>(&Xy[buf][gj], hv, lo, y);
+      modulate1<G, TBL - 1>(&Xy[buf][gj], hv2, lo2g, yc);
+    } else {
+      modulate<G>(&Xy[buf][gj], hv, lo, y, yc);
+    }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       Bs[buf][gj + g][ga] = y[g];
@@ -315,32 +332,34 @@ __device__ __forceinline__ void contract_f32_tile(const ContractArgs& a, TileId 
 
   if (ns > 0) {
     Stager<NT, XW, KS> stg;
-    stg.load(a.v, a.vy, tl.cbase, tl.tau0, tl.yend, hptr(0), tid);
+    stg.load(a.v, a.vy, tl.cbase, tl.tau0, tl.yend, hptr(0), tid, hptr2(0));
     stg.store(&Xh[0][0], &Xy[0][0], tid);
-    const float2 h0 = stg.hv;
-    stg.load(a.v, a.vy, tl.cbase + KS, tl.tau0, tl.yend, hptr(1), tid);
+    const float2 h0 = stg.hv, h02 = stg.hv2;
+    stg.load(a.v, a.vy, tl.cbase + KS, tl.tau0, tl.yend, hptr(1), tid, hptr2(1));
     stg.store(&Xh[1][0], &Xy[1][0], tid);
-    float2 hnext = stg.hv;
+    float2 hnext = stg.hv, hnext2 = stg.hv2;
     __syncthreads();
-    produce(0, h0);
+    produce(0, h0, h02);
     __syncthreads();
     int xb = 0;  // = ks % 3
     for (int ks = 0; ks + 1 < ns; ++ks) {
       const int buf = ks & 1;
       const int xb2 = xb == 0 ? 2 : xb - 1;  // (ks + 2) % 3
-      stg.load(a.v, a.vy, tl.cbase + (int64_t)(ks + 2) * KS, tl.tau0, tl.yend, hptr(ks + 2), tid);
+      stg.load(a.v, a.vy, tl.cbase + (int64_t)(ks + 2) * KS, tl.tau0, tl.yend, hptr(ks + 2), tid,
+               hptr2(ks + 2));
       __builtin_amdgcn_s_setprio(1);  // as in the 16-bit kernel
       mfma_step(xb, buf);
       __builtin_amdgcn_s_setprio(0);
-      produce(buf ^ 1, hnext);
+      produce(buf ^ 1, hnext, hnext2);
       stg.store(&Xh[xb2][0], &Xy[buf][0], tid);
       hnext = stg.hv;
+      hnext2 = stg.hv2;
       xb = xb == 2 ? 0 : xb + 1;
       __syncthreads();
     }
     mfma_step(xb, (ns - 1) & 1);
   }
-  store_tiles<WM, WN, AW>(a, tl.id, tl.tau0, tl.alpha0, wm, wn, lane, acc);
+  store_tiles<WM, WN, AW, TBL>(a, tl.id, tl.tau0, tl.alpha0, wm, wn, lane, acc);
 }
 
 // ----------------------------------------------------------------------------- BF16/FP16 contraction
@@ -357,7 +376,7 @@ __device__ __forceinline__ void contract_f32_tile(const ContractArgs& a, TileId 
 // (cr, sh) at fragment offsets 0 and +4 words, i.e. in 16-byte bank units
 // 8 cr + 2 sh + {0, 1} (mod 16): all sixteen units differ, so the reads are
 // free of bank conflicts.
-template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS, int SCHED>
+template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS, int SCHED, int TBL>
 __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId tid_in) {
   using O = Op<PREC>;
   constexpr int NT = 64 * WAVES_M * WAVES_N;
@@ -386,7 +405,7 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
   const int h = lane >> 5, l32 = lane & 31;
-  const Tile tl(a, tid_in, TW, AW, KS);
+  const Tile tl(a, tid_in, TW, TBL ? 2 * AW : AW, KS);
   const int ns = tl.ns;
 
   const int ga = tid % AW, gj = (tid / AW) * G;
@@ -397,6 +416,15 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
   for (int g = 0; g < G; ++g) lo[g] = aval ? a.Lo[(int64_t)galpha * KS + gj + g] : make_float2(0.f, 0.f);
   const float2* Hrow = a.H + (int64_t)(aval ? galpha : 0) * tl.nsteps;
   auto hptr = [&](int ks) { return Hrow + min(ks, tl.nsteps - 1); };
+  // one table: the thread's second cycle frequency (tile column AW + ga)
+  const int galpha2 = galpha + AW;
+  const bool aval2 = TBL && galpha2 < a.A;
+  float2 lo2[TBL ? G : 1];
+#pragma unroll
+  for (int g = 0; g < (TBL ? G : 1); ++g)
+    lo2[g] = aval2 ? a.Lo[(int64_t)galpha2 * KS + gj + g] : make_float2(0.f, 0.f);
+  const float2* Hrow2 = a.H + (int64_t)(aval2 ? galpha2 : 0) * tl.nsteps;
+  auto hptr2 = [&](int ks) { return TBL ? Hrow2 + min(ks, tl.nsteps - 1) : (const float2*)nullptr; };
 
   // Word offset of this lane's Hankel fragment for the wave's first row block
   // (row R = 2 lag + cr, four samples from lag + 4h, in copy (cr, lag + 4h mod 4)).
@@ -408,7 +436,7 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
     zoff0 = (R & 1) * CO + sh * ZP + (p0 - sh);
   }
 
-  auto produce = [&](int buf, float2 hv) {
+  auto produce = [&](int buf, float2 hv, float2 hv2) {
     // Hankel copies from the FP32 window; unit u -> (grp = u/4, sh = u%4), units
     // past ZU repeat earlier ones (identical values to identical addresses).
 #pragma unroll
@@ -430,7 +458,15 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
     uint32_t py[NB][G], pyc[NB][G];
     {
       float2 y[G], yc[G];
-      modulate<G>(&Xy[buf][gj], hv, lo, y, yc);
+      if (TBL) {
+        float2 lo2g[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) lo2g[g] = lo2[TBL ? g : 0];
+        modulate1<G, TBL - 1>(&Xy[buf][gj], hv, lo, y);
+        modulate1<G, TBL - 1>(&Xy[buf][gj], hv2, lo2g, yc);
+      } else {
+        modulate<G>(&Xy[buf][gj], hv, lo, y, yc);
+      }
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         py[0][g] = O::pack(y[g].x, y[g].y);
@@ -492,26 +528,28 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
 
   if (ns > 0) {
     Stager<NT, XW, KS> stg;
-    stg.load(a.v, a.vy, tl.cbase, tl.tau0, tl.yend, hptr(0), tid);
+    stg.load(a.v, a.vy, tl.cbase, tl.tau0, tl.yend, hptr(0), tid, hptr2(0));
     stg.store(&Xh[0][0], &Xy[0][0], tid);
-    const float2 h0 = stg.hv;
-    stg.load(a.v, a.vy, tl.cbase + KS, tl.tau0, tl.yend, hptr(1), tid);
+    const float2 h0 = stg.hv, h02 = stg.hv2;
+    stg.load(a.v, a.vy, tl.cbase + KS, tl.tau0, tl.yend, hptr(1), tid, hptr2(1));
     stg.store(&Xh[1][0], &Xy[1][0], tid);
-    float2 hnext = stg.hv;
+    float2 hnext = stg.hv, hnext2 = stg.hv2;
     __syncthreads();
-    produce(0, h0);
+    produce(0, h0, h02);
     __syncthreads();
     for (int ks = 0; ks + 1 < ns; ++ks) {
       const int buf = ks & 1;
-      stg.load(a.v, a.vy, tl.cbase + (int64_t)(ks + 2) * KS, tl.tau0, tl.yend, hptr(ks + 2), tid);
+      stg.load(a.v, a.vy, tl.cbase + (int64_t)(ks + 2) * KS, tl.tau0, tl.yend, hptr(ks + 2), tid,
+               hptr2(ks + 2));
       // The wave issuing matrix-core work runs at raised priority; the other
       // resident wave's operand generation fills the issue slots it leaves.
       __builtin_amdgcn_s_setprio(1);
       mfma_step(buf);
       __builtin_amdgcn_s_setprio(0);
-      produce(buf ^ 1, hnext);
+      produce(buf ^ 1, hnext, hnext2);
       stg.store(&Xh[buf][0], &Xy[buf][0], tid);
       hnext = stg.hv;
+      hnext2 = stg.hv2;
       if (SCHED) {
         // Interleave the next step's operand generation with this step's
         // matrix-core instructions so one wave overlaps both.
@@ -527,7 +565,7 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
     }
     mfma_step((ns - 1) & 1);
   }
-  store_tiles<WM, WN, AW>(a, tl.id, tl.tau0, tl.alpha0, wm, wn, lane, acc);
+  store_tiles<WM, WN, AW, TBL>(a, tl.id, tl.tau0, tl.alpha0, wm, wn, lane, acc);
 }
 
 // ----------------------------------------------------------------------------- kernels
@@ -537,14 +575,14 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
 // work items (job, lag tile, alpha tile) from an atomic counter until the
 // list is exhausted.  Every workgroup reaches the exit test each round, so the
 // grid drains whatever the number of items.
-template <int TW, int AW, int WAVES_M, int WAVES_N, int KS>
+template <int TW, int AW, int WAVES_M, int WAVES_N, int KS, int TBL>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_f32(ContractArgs a) {
-  contract_f32_tile<TW, AW, WAVES_M, WAVES_N, KS>(a, tile_of(a));
+  contract_f32_tile<TW, AW, WAVES_M, WAVES_N, KS, TBL>(a, tile_of(a));
 }
 
-template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS, int SCHED>
+template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS, int SCHED, int TBL>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_16(ContractArgs a) {
-  contract_16_tile<PREC, SPLIT, TW, AW, WAVES_M, WAVES_N, KS, SCHED>(a, tile_of(a));
+  contract_16_tile<PREC, SPLIT, TW, AW, WAVES_M, WAVES_N, KS, SCHED, TBL>(a, tile_of(a));
 }
 
 // Takes the next work item; all threads of the workgroup see the same value.
@@ -585,7 +623,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_f32_batch(
     id.chunk = 0;
     id.tt = bi.tt;
     id.at = bi.at;
-    contract_f32_tile<TW, AW, WAVES_M, WAVES_N, KS>(job_args(b, j), id);
+    contract_f32_tile<TW, AW, WAVES_M, WAVES_N, KS, 0>(job_args(b, j), id);
   }
 }
 
@@ -600,7 +638,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void contract_16_batch(B
     id.chunk = 0;
     id.tt = bi.tt;
     id.at = bi.at;
-    contract_16_tile<PREC, SPLIT, TW, AW, WAVES_M, WAVES_N, KS, SCHED>(job_args(b, j), id);
+    contract_16_tile<PREC, SPLIT, TW, AW, WAVES_M, WAVES_N, KS, SCHED, 0>(job_args(b, j), id);
   }
 }
 
@@ -818,7 +856,7 @@ __global__ __launch_bounds__(64, 1) void contract_rg(ContractArgs a) {
       }
     }
   }
-  store_tiles<RB, 2 * NA, AW>(a, tl.id, tl.tau0, tl.alpha0, 0, 0, lane, acc);
+  store_tiles<RB, 2 * NA, AW, 0>(a, tl.id, tl.tau0, tl.alpha0, 0, 0, lane, acc);
 }
 
 template <int PREC, int SPLIT, int RB, int NA, int KS>
@@ -829,16 +867,16 @@ hipError_t launch_rg(const ContractArgs& a, int grid, hipStream_t st) {
 
 // ----------------------------------------------------------------------------- config table
 
-template <int TW, int AW, int WAVES_M, int WAVES_N, int KS>
+template <int TW, int AW, int WAVES_M, int WAVES_N, int KS, int TBL = 0>
 hipError_t launch_f32(const ContractArgs& a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((contract_f32<TW, AW, WAVES_M, WAVES_N, KS>), dim3(grid),
+  hipLaunchKernelGGL((contract_f32<TW, AW, WAVES_M, WAVES_N, KS, TBL>), dim3(grid),
                      dim3(64 * WAVES_M * WAVES_N), 0, st, a);
   return hipGetLastError();
 }
 
-template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS, int SCHED>
+template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS, int SCHED, int TBL = 0>
 hipError_t launch_16(const ContractArgs& a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((contract_16<PREC, SPLIT, TW, AW, WAVES_M, WAVES_N, KS, SCHED>), dim3(grid),
+  hipLaunchKernelGGL((contract_16<PREC, SPLIT, TW, AW, WAVES_M, WAVES_N, KS, SCHED, TBL>), dim3(grid),
                      dim3(64 * WAVES_M * WAVES_N), 0, st, a);
   return hipGetLastError();
 }
@@ -892,6 +930,21 @@ int grid_16_batch() {
 #define CFG_RG(P, PN, SP, RB, NA, KS)                                                      \
   {P, SP, 16 * RB, 32 * NA, KS, 64, &launch_rg<P, SP, RB, NA, KS>,                           \
    PN "_s" #SP "_t" #RB "x16_a" #NA "x32_reg_k" #KS, nullptr, nullptr}
+// One-table tiles (TBL = 1: R, 2: Rc): 2 AW cycle frequencies of one table
+// per tile, single states only.
+#define CFG_F32_T(TW, AW, WMW, WNW, KS, TBL, TN)                                            \
+  {PREC_F32, 0, TW, AW, KS, 64 * WMW * WNW, &launch_f32<TW, AW, WMW, WNW, KS, TBL>,         \
+   "f32_t" #TW "_a" #AW "_w" #WMW "x" #WNW "_k" #KS "_" TN, nullptr, nullptr, TBL}
+#define CFG_16_T(P, PN, SP, TW, AW, WMW, WNW, KS, SC, TBL, TN)                               \
+  {P, SP, TW, AW, KS, 64 * WMW * WNW, &launch_16<P, SP, TW, AW, WMW, WNW, KS, SC, TBL>,     \
+   PN "_s" #SP "_t" #TW "_a" #AW "_w" #WMW "x" #WNW "_k" #KS "_i" #SC "_" TN, nullptr, nullptr, TBL}
+#define CFG_T_ALL(TW, AW, WMW, WNW, TBL, TN)                                        \
+  CFG_F32_T(TW, AW, WMW, WNW, 16, TBL, TN),                                         \
+  CFG_16_T(PREC_BF16, "bf16", 0, TW, AW, WMW, WNW, 32, 0, TBL, TN),                 \
+  CFG_16_T(PREC_BF16, "bf16", 1, TW, AW, WMW, WNW, 32, 0, TBL, TN),                 \
+  CFG_16_T(PREC_F16, "f16", 0, TW, AW, WMW, WNW, 32, 0, TBL, TN),                   \
+  CFG_16_T(PREC_F16, "f16", 1, TW, AW, WMW, WNW, 32, 0, TBL, TN)
+
 #define CFG_RG_ALL(RB, NA, KS)                  \
   CFG_RG(PREC_BF16, "bf16", 0, RB, NA, KS),     \
   CFG_RG(PREC_BF16, "bf16", 1, RB, NA, KS),     \
@@ -917,6 +970,12 @@ static const KernelCfg g_cfgs[] = {
     CFG_RG_ALL(8, 1, 32),
     CFG_16_ALL(128, 64, 2, 2, 32, 1),
     CFG_16_ALL(128, 64, 2, 2, 32, 0),
+    CFG_T_ALL(128, 64, 4, 1, 1, "R"),
+    CFG_T_ALL(64, 64, 2, 1, 1, "R"),
+    CFG_T_ALL(32, 64, 1, 2, 1, "R"),
+    CFG_T_ALL(128, 64, 4, 1, 2, "Rc"),
+    CFG_T_ALL(64, 64, 2, 1, 2, "Rc"),
+    CFG_T_ALL(32, 64, 1, 2, 2, "Rc"),
 };
 
 const KernelCfg* kernel_cfgs(int* n) {
@@ -956,10 +1015,11 @@ __global__ void phase_kernel(const double* alpha_r, int A, int64_t base0, int Kc
 
 // S += sum_c part[c] * E[c] in FP64, chunks in ascending order (first: S starts at 0).
 __global__ void accumulate_kernel(double2* S, const float2* part, const double2* E, int T, int A,
-                                  int nc, int first) {
+                                  int nc, int first, int tbl) {
   const int64_t n2 = 2 * (int64_t)T * A;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n2) return;
+  // tbl 0: both tables; 1 / 2: only the elements of table R / Rc
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + (tbl ? (int64_t)(tbl - 1) * T * A : 0);
+  if (i >= (tbl ? (int64_t)tbl * T * A : n2)) return;
   const int a = (int)(i % A);
   double2 s = first ? make_double2(0.0, 0.0) : S[i];
   for (int c = 0; c < nc; ++c) {
@@ -1159,10 +1219,10 @@ hipError_t launch_phase(const double* alpha_r, int A, int64_t base0, int Kc, int
 }
 
 hipError_t launch_accumulate(double2* S, const float2* part, const double2* E, int T, int A, int nc,
-                             int first, hipStream_t st) {
-  const int64_t n = 2 * (int64_t)T * A;
+                             int first, int tbl, hipStream_t st) {
+  const int64_t n = (tbl ? 1 : 2) * (int64_t)T * A;
   hipLaunchKernelGGL(accumulate_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, S, part, E, T, A,
-                     nc, first);
+                     nc, first, tbl);
   return hipGetLastError();
 }
 

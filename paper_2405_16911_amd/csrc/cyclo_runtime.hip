@@ -59,6 +59,7 @@ struct cyc_state {
   double2* E = nullptr;
   int64_t L = 0;
   int64_t nc = 0;  // products committed
+  int tbl = 0;     // tables computed: 0 both, 1 R only, 2 Rc only
   bool poisoned = false;
   // contraction-kernel timing
   bool prof = false;
@@ -140,28 +141,29 @@ void tune_store(const TuneKey& k, const std::string& name) {
   std::fclose(f);
 }
 
-// Chooses the contraction kernel for (precision, split, T, A): an explicit
-// CYC_KERNEL_CFG index if it implements the mode, else the tuning cache, else
-// the first configuration whose lag tile fits T.
-int pick_cfg(int prec, int split, int T, int A) {
+// Chooses the contraction kernel for (precision, split, tables, T, A): an
+// explicit CYC_KERNEL_CFG index if it implements the mode, else the tuning
+// cache, else the first configuration whose lag tile fits T.  The cache keys
+// the mode as (prec, split + 2 tbl).
+int pick_cfg(int prec, int split, int tbl, int T, int A) {
   int n = 0;
   const KernelCfg* c = kernel_cfgs(&n);
+  auto mode_ok = [&](int i) { return c[i].prec == prec && c[i].split == split && c[i].tbl == tbl; };
   const int64_t forced = env_i64("CYC_KERNEL_CFG", -1);
-  if (forced >= 0 && forced < n && c[forced].prec == prec && c[forced].split == split)
-    return (int)forced;
+  if (forced >= 0 && forced < n && mode_ok((int)forced)) return (int)forced;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_locked();
-    auto it = g_tune.find(TuneKey(device_arch(), prec, split, T, a_bucket(A)));
+    auto it = g_tune.find(TuneKey(device_arch(), prec, split + 2 * tbl, T, a_bucket(A)));
     if (it != g_tune.end()) {
       const int i = cfg_by_name(it->second);
-      if (i >= 0 && c[i].prec == prec && c[i].split == split) return i;
+      if (i >= 0 && mode_ok(i)) return i;
     }
   }
   const int want_tw = T > 64 ? 128 : (T > 32 ? 64 : 32);
   int best = -1;
   for (int i = 0; i < n; ++i) {
-    if (c[i].prec != prec || c[i].split != split || c[i].tw != want_tw || c[i].aw != 64) continue;
+    if (!mode_ok(i) || c[i].tw != want_tw || c[i].aw != 64) continue;
     if (best < 0 || (c[best].nthreads != 256 && c[i].nthreads == 256)) best = i;
   }
   return best;
@@ -170,7 +172,7 @@ int pick_cfg(int prec, int split, int T, int A) {
 }  // namespace
 
 // Shared with the batch runtime.
-int cyc_pick_cfg(int prec, int split, int T, int A) { return pick_cfg(prec, split, T, A); }
+int cyc_pick_cfg(int prec, int split, int T, int A) { return pick_cfg(prec, split, 0, T, A); }
 
 namespace {
 
@@ -216,7 +218,8 @@ static hipError_t run_contract(cyc_state* s, const VSrc& v, const VSrc& vy, int6
   a.A = s->A;
   a.Kc = s->Kc;
   a.n_tt = (s->T + cfg.tw - 1) / cfg.tw;
-  a.n_at = (s->A + cfg.aw - 1) / cfg.aw;
+  const int atile = cfg.tbl ? 2 * cfg.aw : cfg.aw;  // cycle frequencies per tile
+  a.n_at = (s->A + atile - 1) / atile;
   a.n_chunks = nch;
   a.H = s->H;
   a.Lo = s->Lo;
@@ -262,11 +265,14 @@ static int create_state(cyc_state** out, const double* alphas_host, int32_t n_al
   if (n_hops < 0 || n_hops > 4096 || (n_hops > 0 && (hop < 32 || hop > (1 << 20) || hop % 32 != 0)))
     return CYC_EINVAL;
   if (lag_min < -kMaxLagShift || lag_min > kMaxLagShift) return CYC_EINVAL;
-  if (flags & ~(CYC_OP_MASK | CYC_TW_SPLIT | CYC_OUT_C128)) return CYC_EINVAL;
+  if (flags & ~(CYC_OP_MASK | CYC_TW_SPLIT | CYC_OUT_C128 | CYC_TBL_R | CYC_TBL_RCONJ)) return CYC_EINVAL;
   const int prec = (int)(flags & CYC_OP_MASK);
   if (prec == 3) return CYC_EINVAL;
   const int split = (flags & CYC_TW_SPLIT) ? 1 : 0;
   if (split && prec == PREC_F32) return CYC_EUNSUPPORTED;
+  const bool want_r = flags & CYC_TBL_R, want_rc = flags & CYC_TBL_RCONJ;
+  const int tbl = want_r == want_rc ? 0 : (want_r ? 1 : 2);
+  if (tbl && n_hops > 0) return CYC_EUNSUPPORTED;  // the window form keeps both tables
   for (int32_t i = 0; i < n_alpha; ++i)
     if (!std::isfinite(alphas_host[i])) return CYC_EINVAL;
 
@@ -280,7 +286,8 @@ static int create_state(cyc_state** out, const double* alphas_host, int32_t n_al
   s->dx = std::max<int64_t>(0, lag_min);
   s->dy = std::max<int64_t>(0, -lag_min);
   s->lagabs = lag_min < 0 ? -lag_min : lag_min;
-  s->cfg = pick_cfg(prec, split, n_lag, n_alpha);
+  s->tbl = tbl;
+  s->cfg = pick_cfg(prec, split, tbl, n_lag, n_alpha);
   if (s->cfg < 0) {
     delete s;
     return CYC_EUNSUPPORTED;
@@ -413,7 +420,8 @@ int push_xy(cyc_state* s, const float2* x, const float2* y, int64_t n, hipStream
     if (launch_phase(s->alpha_r, s->A, abs0 + s->dy, s->Kc, nch, s->E, st) != hipSuccess ||
         run_contract(s, vx, vy, done * s->Kc, (int64_t)nch * s->Kc, nch, st) != hipSuccess ||
         (s->win > 0 ? launch_window_store(s->ring, s->part, s->E, s->T, s->A, nch, abs0 / s->Kc, s->win, st)
-                    : launch_accumulate(s->S, s->part, s->E, s->T, s->A, nch, abs0 == 0 ? 1 : 0, st)) != hipSuccess)
+                    : launch_accumulate(s->S, s->part, s->E, s->T, s->A, nch, abs0 == 0 ? 1 : 0, s->tbl, st)) !=
+          hipSuccess)
       return fail_device(s);
     done += nch;
   }
@@ -451,6 +459,7 @@ int cyc_push2(cyc_state* s, const void* d_x, const void* d_y, int64_t n, void* s
 int cyc_read(cyc_state* s, void* d_R, void* d_Rc, int64_t* n_used, void* stream) {
   if (!s) return CYC_EINVAL;
   if (s->poisoned) return CYC_ESTATE;
+  if ((s->tbl == 1 && d_Rc) || (s->tbl == 2 && d_R)) return CYC_EINVAL;  // a table the state does not keep
   hipStream_t st = as_stream(stream);
   const int c128 = (s->flags & CYC_OUT_C128) ? 1 : 0;
   const int64_t tbytes = (int64_t)s->T * s->A * (c128 ? 16 : 8);
@@ -557,7 +566,9 @@ int cyc_kernel_cfg_info(int32_t idx, uint32_t* flags, int32_t* lag_tile, int32_t
   int n = 0;
   const KernelCfg* c = kernel_cfgs(&n);
   if (idx < 0 || idx >= n) return CYC_EINVAL;
-  if (flags) *flags = (uint32_t)c[idx].prec | (c[idx].split ? CYC_TW_SPLIT : 0u);
+  if (flags)
+    *flags = (uint32_t)c[idx].prec | (c[idx].split ? CYC_TW_SPLIT : 0u) |
+             (c[idx].tbl == 1 ? CYC_TBL_R : 0u) | (c[idx].tbl == 2 ? CYC_TBL_RCONJ : 0u);
   if (lag_tile) *lag_tile = c[idx].tw;
   if (alpha_tile) *alpha_tile = c[idx].aw;
   if (threads) *threads = c[idx].nthreads;
@@ -570,7 +581,7 @@ int cyc_set_kernel_cfg(cyc_state* s, int32_t idx) {
   const KernelCfg* c = kernel_cfgs(&n);
   if (!s || idx < 0 || idx >= n) return CYC_EINVAL;
   const KernelCfg& cur = c[s->cfg];
-  if (c[idx].prec != cur.prec || c[idx].split != cur.split || c[idx].ks != cur.ks)
+  if (c[idx].prec != cur.prec || c[idx].split != cur.split || c[idx].ks != cur.ks || c[idx].tbl != cur.tbl)
     return CYC_EUNSUPPORTED;
   s->cfg = idx;
   return CYC_OK;
@@ -600,6 +611,7 @@ int cyc_autotune(int32_t n_alpha, int32_t n_lag, uint32_t flags, int32_t* best_c
   int n = 0;
   const KernelCfg* c = kernel_cfgs(&n);
   const int prec = (int)(flags & CYC_OP_MASK), split = (flags & CYC_TW_SPLIT) ? 1 : 0;
+  const int tbl = s->tbl;
   std::vector<int> cand;
   for (int i = 0; i < n; ++i)
     if (c[i].prec == prec && c[i].split == split && cyc_set_kernel_cfg(s, i) == CYC_OK) cand.push_back(i);
@@ -646,7 +658,7 @@ int cyc_autotune(int32_t n_alpha, int32_t n_lag, uint32_t flags, int32_t* best_c
   cyc_destroy(s);
   if (rc != CYC_OK) return rc;
   if (best < 0) return CYC_EUNSUPPORTED;
-  tune_store(TuneKey(device_arch(), prec, split, n_lag, a_bucket(n_alpha)), c[best].name);
+  tune_store(TuneKey(device_arch(), prec, split + 2 * tbl, n_lag, a_bucket(n_alpha)), c[best].name);
   if (best_cfg) *best_cfg = best;
   if (best_ms) *best_ms = bms;
   return CYC_OK;

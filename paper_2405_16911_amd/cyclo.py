@@ -27,6 +27,8 @@ CYC_OP_BF16 = 0x1
 CYC_OP_FP16 = 0x2
 CYC_TW_SPLIT = 0x4
 CYC_OUT_C128 = 0x8
+CYC_TBL_R = 0x10
+CYC_TBL_RCONJ = 0x20
 
 #: exported symbols and their ctypes signatures (restype, argtypes)
 SIGNATURES = {
@@ -264,9 +266,17 @@ class CyclicStream:
     def push(self, x, stream=None):
         cyc_push(self._s, x, stream)
 
-    def read(self, stream=None, which=(True, True)):
-        """Returns (R, Rc, n_used) as new [T, A] complex tensors on the GPU."""
+    def tables(self):
+        """(keeps R, keeps Rc) from the table flags (neither or both flags: both)."""
+        r, rc = bool(self.flags & CYC_TBL_R), bool(self.flags & CYC_TBL_RCONJ)
+        return (True, True) if r == rc else (r, rc)
+
+    def read(self, stream=None, which=None):
+        """Returns (R, Rc, n_used) as new [T, A] complex tensors on the GPU (None for a
+        table not asked for; by default every table the state keeps)."""
         import torch
+        if which is None:
+            which = self.tables()
         dt = torch.complex128 if self.flags & CYC_OUT_C128 else torch.complex64
         shape = (self.T, self.alphas.size)
         R = torch.empty(shape, dtype=dt, device="cuda") if which[0] else None

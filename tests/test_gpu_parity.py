@@ -155,8 +155,11 @@ def test_every_kernel_configuration(cy):
     x = siggen.qpsk_rrc_stream(n=2 * 4096 + 555, seed=9)
     alphas = np.random.default_rng(1).uniform(-0.5, 0.5, size=A)
     by_mode = {}
-    for idx in range(cy.cyc_kernel_cfg_count()):
-        info = cy.cyc_kernel_cfg_info(idx)
+    tbl_bits = cy.CYC_TBL_R | cy.CYC_TBL_RCONJ
+    infos = [cy.cyc_kernel_cfg_info(i) for i in range(cy.cyc_kernel_cfg_count())]
+    # two-table configurations first, so every one-table configuration has its reference
+    for info in sorted(infos, key=lambda i: bool(i["flags"] & tbl_bits)):
+        idx = info["index"]
         st = cy.CyclicStream(alphas, T, info["flags"])
         st.set_kernel_cfg(idx)
         xd = _dev(x)
@@ -165,10 +168,19 @@ def test_every_kernel_configuration(cy):
         R, Rc, n = st.read()
         torch.cuda.synchronize()
         st.close()
-        R, Rc = R.cpu().numpy(), Rc.cpu().numpy()
         print(f"  cfg {idx} {info['name']}", flush=True)
+        mode = info["flags"] & ~tbl_bits
+        if info["flags"] & tbl_bits:
+            # one table: bitwise the two-table configurations' table
+            ref = by_mode[mode]
+            if info["flags"] & cy.CYC_TBL_R:
+                assert Rc is None and np.array_equal(R.cpu().numpy(), ref[0]), info["name"]
+            else:
+                assert R is None and np.array_equal(Rc.cpu().numpy(), ref[1]), info["name"]
+            continue
+        R, Rc = R.cpu().numpy(), Rc.cpu().numpy()
         _check(x, alphas, T, R, Rc, n, info["flags"], 4096, info["name"])
-        ref = by_mode.setdefault(info["flags"], (R, Rc))
+        ref = by_mode.setdefault(mode, (R, Rc))
         assert np.array_equal(ref[0], R) and np.array_equal(ref[1], Rc), info["name"]
 
 
@@ -322,3 +334,53 @@ def test_config2_full_size_sampled_cells(cy, flags):
     # the strongest features of QPSK-RRC at 4 samples/symbol: alpha = 0 and +-1/4
     m = np.abs(R[2])
     assert set(np.argsort(-m)[:3]) == {2048, 1024, 3072}
+
+
+@pytest.mark.parametrize("flags", [0, 1, 2, 2 | 4])
+@pytest.mark.parametrize("T,A", [(128, 150), (40, 200), (9, 65)])
+def test_one_table_states(cy, flags, T, A):
+    """CYC_TBL_R / CYC_TBL_RCONJ: a state that keeps one table contracts only
+    that table; its table matches the oracle within the bound and equals the
+    two-table state's bit for bit (same operands, same summation order), and
+    reading the table it does not keep is refused."""
+    x = siggen.qpsk_rrc_stream(n=3 * 4096 + 321 + T, seed=17)
+    alphas = np.random.default_rng(T + A).uniform(-0.5, 0.5, size=A)
+    both = _run(cy, x, alphas, T, flags=flags, splits=[5000, x.size - 5000])
+    Ro, Rco, no = cyclic_tables(x, alphas, T)
+    for which, tflag in ((0, cy.CYC_TBL_R), (1, cy.CYC_TBL_RCONJ)):
+        st = cy.CyclicStream(alphas, T, flags | tflag)
+        xd = _dev(x)
+        st.push(xd[:5000])
+        st.push(xd[5000:])
+        got, other, n = st.read()
+        torch.cuda.synchronize()
+        if which == 1:
+            got, other = other, got
+        assert other is None and n == no
+        got = got.cpu().numpy()
+        assert np.array_equal(got, both[which]), (which, tflag)
+        ref = Ro if which == 0 else Rco
+        check_cells(x, T, flags, both[3]["chunk"], got, got, ref, ref, f"table {which} flags {flags}")
+        # the other table is not kept
+        import ctypes
+        d = torch.empty((T, A), dtype=torch.complex64, device="cuda")
+        n_used = ctypes.c_int64(0)
+        args = (None, ctypes.c_void_p(d.data_ptr())) if which == 0 else (ctypes.c_void_p(d.data_ptr()), None)
+        assert cy.lib().cyc_read(st._s, *args, ctypes.byref(n_used), None) == cy.CYC_EINVAL
+        st.close()
+
+
+def test_one_table_flags_are_refused_where_unsupported(cy):
+    import ctypes
+    al = np.array([0.1, 0.2])
+    out = ctypes.c_void_p()
+    L = cy.lib()
+    ap = al.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert L.cyc_create_window(ctypes.byref(out), al.ctypes.data_as(ctypes.c_void_p), 2, 4, 64, 2,
+                               cy.CYC_TBL_R, None) == cy.CYC_EUNSUPPORTED
+    offs = (ctypes.c_int64 * 2)(0, 2)
+    assert L.cyc_batch_create(ctypes.byref(out), 1, offs, ap, 4, cy.CYC_TBL_RCONJ, None) == cy.CYC_EUNSUPPORTED
+    # both flags = both tables
+    st = cy.CyclicStream(al, 4, cy.CYC_TBL_R | cy.CYC_TBL_RCONJ)
+    assert st.tables() == (True, True)
+    st.close()
