@@ -421,6 +421,9 @@ def main():
             bw = batch_workload(args.batch_streams)
             forms["batch"] = dict(workload=bw["desc"], runs=[run_batch(bw, p, max(1, args.steps), args.warmup)
                                                              for p in args.batch_precisions.split(",")])
+        if "proposal" in forms_wanted:
+            forms["proposal"] = run_proposal(args.proposal_train, pool)
+            pool.close()
         print(json.dumps({"forms": forms}), flush=True)
         return
     wl = workload(args.workload)

@@ -28,6 +28,12 @@
  *  - A state is not thread-safe; distinct states are independent.
  *  - After a device-side failure the state is poisoned: every call returns
  *    CYC_ESTATE until cyc_reset().
+ *  - A push may run its FP64 accumulation on a stream of the state's own,
+ *    ordered by events after the push's contraction on `stream`; the next
+ *    read (and any later push that reuses the workspace) waits for it on its
+ *    own stream, so results are as if everything ran on `stream`.
+ *    cyc_destroy synchronises the device.  CYC_SERIAL_ACC=1 at creation keeps
+ *    every step on `stream`.
  */
 #ifndef CYCLO_H
 #define CYCLO_H

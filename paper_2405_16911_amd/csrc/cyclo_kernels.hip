@@ -116,9 +116,11 @@ __device__ __forceinline__ TileId tile_of(const ContractArgs& a) {
   return r;
 }
 
-// Stores one wave's 32x32 accumulator blocks: rows (t, re/im) interleaved,
-// columns q < AW -> table 0 (R), q >= AW -> table 1 (Rc).
-template <int WM, int WN, int AW>
+// Stores one wave's 32x32 accumulator blocks: rows (t, re/im) interleaved;
+// with both tables (TBL = 0) columns q < AW -> table 0 (R) and q >= AW ->
+// table 1 (Rc) of the same AW cycle frequencies, with one table (TBL = 1: R,
+// 2: Rc) column q is that table at the tile's cycle frequency q (2 AW of them).
+template <int WM, int WN, int AW, int TBL>
 __device__ __forceinline__ void store_tiles(const ContractArgs& a, const TileId& id, int tau0,
                                             int alpha0, int wm, int wn, int lane,
                                             const f32x16 (&acc)[WM][WN]) {
@@ -128,8 +130,8 @@ __device__ __forceinline__ void store_tiles(const ContractArgs& a, const TileId&
 #pragma unroll
   for (int cb = 0; cb < WN; ++cb) {
     const int q = (wn * WN + cb) * 32 + l32;
-    const int table = q >= AW ? 1 : 0;
-    const int alpha = alpha0 + (q - table * AW);
+    const int table = TBL ? TBL - 1 : (q >= AW ? 1 : 0);
+    const int alpha = alpha0 + (TBL ? q : q - table * AW);
     if (alpha >= a.A) continue;
     float2* tb = base + table * TA + alpha;
 #pragma unroll
@@ -165,11 +167,12 @@ struct Stager {
   static constexpr int R = (N + NT - 1) / NT;
   float2 r[R];
   bool ok[R];
-  float2 hv;
+  float2 hv, hv2;
   // vx: the leading samples (Hankel window), vy: the trailing samples (the
-  // modulated operand); the same array for one input.
+  // modulated operand); the same array for one input.  hp2: the twiddle entry
+  // of the thread's second cycle frequency (one-table tiles), else nullptr.
   __device__ __forceinline__ void load(const VSrc& vx, const VSrc& vy, int64_t s0, int tau0, int64_t yend,
-                                       const float2* hp, int tid) {
+                                       const float2* hp, int tid, const float2* hp2 = nullptr) {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int idx = tid + i * NT;
@@ -182,6 +185,7 @@ struct Stager {
       ok[i] = valid;
     }
     hv = *hp;
+    if (hp2) hv2 = *hp2;
   }
   __device__ __forceinline__ void store(float2* Xh, float2* Xy, int tid) const {
 #pragma unroll
@@ -211,6 +215,21 @@ __device__ __forceinline__ void modulate(const float2* xs, float2 hv, const floa
   }
 }
 
+
+// One table's modulated operand for G consecutive samples of one alpha, with
+// the same roundings as modulate: Y = conj(x) W (CONJ = 0, table R) or
+// Yc = x W (CONJ = 1, table Rc).
+template <int G, int CONJ>
+__device__ __forceinline__ void modulate1(const float2* xs, float2 hv, const float2 (&lo)[G], float2 (&y)[G]) {
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const float2 xv = xs[g];
+    const float2 w = cmul(hv, lo[g]);
+    const float t1 = xv.y * w.y, t2 = xv.y * w.x;
+    y[g] = CONJ ? make_float2(__fmaf_rn(xv.x, w.x, -t1), __fmaf_rn(xv.x, w.y, t2))
+                : make_float2(__fmaf_rn(xv.x, w.x, t1), __fmaf_rn(xv.x, w.y, -t2));
+  }
+}
 
 // Common per-workgroup set-up.
 struct Tile {
@@ -553,12 +572,14 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
       if (SCHED) {
         // Interleave the next step's operand generation with this step's
         // matrix-core instructions so one wave overlaps both.
+        // SCHED = 1: four VALU instructions per MFMA, else SCHED of them
         constexpr int NMF = WM * WN * (KS / 8) * NB;
+        constexpr int NV = SCHED == 1 ? 4 : SCHED;
 #pragma unroll
         for (int i = 0; i < NMF; ++i) {
-          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-          __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // VALU
-          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+          __builtin_amdgcn_sched_group_barrier(0x002, NV, 0);  // VALU
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
         }
       }
       __syncthreads();
@@ -970,6 +991,8 @@ static const KernelCfg g_cfgs[] = {
     CFG_RG_ALL(8, 1, 32),
     CFG_16_ALL(128, 64, 2, 2, 32, 1),
     CFG_16_ALL(128, 64, 2, 2, 32, 0),
+    CFG_16_ALL(64, 64, 2, 2, 32, 8),
+    CFG_16_ALL(64, 64, 2, 2, 32, 6),
     CFG_T_ALL(128, 64, 4, 1, 1, "R"),
     CFG_T_ALL(64, 64, 2, 1, 1, "R"),
     CFG_T_ALL(32, 64, 1, 2, 1, "R"),

@@ -61,6 +61,18 @@ struct cyc_state {
   int64_t nc = 0;  // products committed
   int tbl = 0;     // tables computed: 0 both, 1 R only, 2 Rc only
   bool poisoned = false;
+  // Overlap: the workspace is split in two halves; each push launch contracts
+  // into one half on the caller's stream, and the FP64 accumulation of that
+  // half runs on `side` while the next launch contracts into the other half.
+  // Events order it: ev_part[h] (contraction into h done) -> accumulation of
+  // h -> ev_acc[h] (h free again).  side == nullptr: everything on the
+  // caller's stream (window states, a one-chunk workspace, CYC_SERIAL_ACC=1).
+  hipStream_t side = nullptr;
+  hipEvent_t ev_part[2] = {nullptr, nullptr};
+  hipEvent_t ev_acc[2] = {nullptr, nullptr};
+  bool acc_used[2] = {false, false};
+  int half = 0, last_half = -1;
+  int maxc_half = 0;
   // contraction-kernel timing
   bool prof = false;
   std::vector<hipEvent_t> ev;  // start/end pairs
@@ -179,6 +191,11 @@ namespace {
 void free_state(cyc_state* s) {
   if (!s) return;
   for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+  for (int h = 0; h < 2; ++h) {
+    if (s->ev_part[h]) (void)hipEventDestroy(s->ev_part[h]);
+    if (s->ev_acc[h]) (void)hipEventDestroy(s->ev_acc[h]);
+  }
+  if (s->side) (void)hipStreamDestroy(s->side);
   (void)hipFree(s->alpha_r);
   (void)hipFree(s->Lo);
   (void)hipFree(s->H);
@@ -206,7 +223,7 @@ int fail_device(cyc_state* s) {
 }  // namespace
 
 static hipError_t run_contract(cyc_state* s, const VSrc& v, const VSrc& vy, int64_t v_off, int64_t n_prod,
-                               int nch, hipStream_t st) {
+                               int nch, hipStream_t st, float2* part = nullptr) {
   int ncfg = 0;
   const KernelCfg& cfg = kernel_cfgs(&ncfg)[s->cfg];
   ContractArgs a;
@@ -223,7 +240,7 @@ static hipError_t run_contract(cyc_state* s, const VSrc& v, const VSrc& vy, int6
   a.n_chunks = nch;
   a.H = s->H;
   a.Lo = s->Lo;
-  a.part = s->part;
+  a.part = part ? part : s->part;
   const int64_t grid = (int64_t)a.n_tt * a.n_at * nch;
   if (grid <= 0 || grid > 0x7fffffff) return hipErrorInvalidValue;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -339,6 +356,19 @@ static int create_state(cyc_state** out, const double* alphas_host, int32_t n_al
         hipStreamSynchronize(st) != hipSuccess)
       rc = CYC_EDEVICE;
   }
+  if (rc == CYC_OK && s->win == 0 && s->maxc >= 2 && env_i64("CYC_SERIAL_ACC", 0) == 0) {
+    // default-priority stream and timing-free events for the overlapped accumulation
+    bool ok = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) == hipSuccess;
+    for (int h = 0; h < 2 && ok; ++h)
+      ok = hipEventCreateWithFlags(&s->ev_part[h], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&s->ev_acc[h], hipEventDisableTiming) == hipSuccess;
+    if (ok) {
+      s->maxc_half = s->maxc / 2;
+    } else {
+      (void)hipGetLastError();
+      rc = CYC_ENOMEM;
+    }
+  }
   delete[] ar;
   if (rc != CYC_OK) {
     (void)hipGetLastError();
@@ -402,6 +432,18 @@ hipError_t keep_input(const cyc_state* s, float2* const* bufs, const VSrc& v, in
   return cnt > 0 ? launch_vcopy(v, shift, cnt, bufs[s->cur ^ 1], st) : hipSuccess;
 }
 
+bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+// Orders `st` after every accumulation issued on the side stream (the side
+// stream is in order, so the last one covers them all).
+hipError_t join_side(cyc_state* s, hipStream_t st) {
+  if (!s->side || s->last_half < 0) return hipSuccess;
+  return hipStreamWaitEvent(st, s->ev_acc[s->last_half], 0);
+}
+
 // Push of n samples of the leading input x and the trailing input y (y == x
 // for one-input states).  Products n (absolute) pair x[n + dx + t] with
 // y[n + dy] and are committed in chunks aligned to [c Kc, (c + 1) Kc); the
@@ -414,7 +456,30 @@ int push_xy(cyc_state* s, const float2* x, const float2* y, int64_t n, hipStream
   const VSrc vx = input_src(s, s->pend, s->dx, x, n, &px, &sx);
   const VSrc vy = s->two ? input_src(s, s->pendy, s->dy, y, n, &py, &sy) : vx;
 
-  for (int64_t done = 0; done < chunks_new;) {
+  const bool overlap = s->side && chunks_new > 0 && !capturing(st);
+  if (!overlap && chunks_new > 0 && join_side(s, st) != hipSuccess) return fail_device(s);
+  for (int64_t done = 0; overlap && done < chunks_new;) {
+    // contraction into one workspace half here, its accumulation on the side stream
+    const int h = s->half;
+    const int nch = (int)std::min<int64_t>(s->maxc_half, chunks_new - done);
+    const int64_t abs0 = s->nc + done * s->Kc;
+    const int64_t TA2 = 2 * (int64_t)s->T * s->A;
+    float2* part = s->part + (int64_t)h * s->maxc_half * TA2;
+    double2* E = s->E + (int64_t)h * s->maxc_half * s->A;
+    if ((s->acc_used[h] && hipStreamWaitEvent(st, s->ev_acc[h], 0) != hipSuccess) ||
+        run_contract(s, vx, vy, done * s->Kc, (int64_t)nch * s->Kc, nch, st, part) != hipSuccess ||
+        hipEventRecord(s->ev_part[h], st) != hipSuccess ||
+        hipStreamWaitEvent(s->side, s->ev_part[h], 0) != hipSuccess ||
+        launch_phase(s->alpha_r, s->A, abs0 + s->dy, s->Kc, nch, E, s->side) != hipSuccess ||
+        launch_accumulate(s->S, part, E, s->T, s->A, nch, abs0 == 0 ? 1 : 0, s->tbl, s->side) != hipSuccess ||
+        hipEventRecord(s->ev_acc[h], s->side) != hipSuccess)
+      return fail_device(s);
+    s->acc_used[h] = true;
+    s->last_half = h;
+    s->half ^= 1;
+    done += nch;
+  }
+  for (int64_t done = 0; !overlap && done < chunks_new;) {
     const int nch = (int)std::min<int64_t>(s->maxc, chunks_new - done);
     const int64_t abs0 = s->nc + done * s->Kc;
     if (launch_phase(s->alpha_r, s->A, abs0 + s->dy, s->Kc, nch, s->E, st) != hipSuccess ||
@@ -491,6 +556,7 @@ int cyc_read(cyc_state* s, void* d_R, void* d_Rc, int64_t* n_used, void* stream)
       return fail_device(s);
     return CYC_OK;
   }
+  if (join_side(s, st) != hipSuccess) return fail_device(s);
   const int64_t m = nu - s->nc;  // products of the pending partial chunk, < Kc
   if (m > 0) {
     VSrc vx;
