@@ -328,7 +328,7 @@ def run_grid(wl, steps: int, warmup: int):
                 ms_per_step=1e3 * dt, arithmetic="FP64 fold and FFT", exact_on="uniform grids, A a power of two")
 
 
-def run_proposal(n_train: int, pool):
+def run_proposal(n_train: int, pool, compare_no_local: bool = False):
     """Learned proposal trained in this run, then timed against the full fine grid.
 
     Windows of 65536 mixed-modulation samples, labels from the full-grid
@@ -340,7 +340,8 @@ def run_proposal(n_train: int, pool):
     """
     from paper_2405_16911_amd import proposal
     r = proposal.run(n_train=n_train, n_val=2048, n_test=2048, epochs=30, batch=128, lr=2e-3, wd=0.1, seed=5,
-                     target_miss=0.01, log=lambda m: print(m, file=sys.stderr, flush=True), pool=pool)
+                     target_miss=0.01, log=lambda m: print(m, file=sys.stderr, flush=True), pool=pool,
+                     compare_no_local=compare_no_local)
     ev, sp = r["eval"], r["speed"]
     return dict(workload="mixed_gmsk_psk_ofdm_window65536_fine65536_T64",
                 metric="learned-proposal vs full-grid speedup at equal error",
@@ -361,7 +362,8 @@ def run_proposal(n_train: int, pool):
                 proposal_ms_per_window=1e3 * sp["proposal_path_s"] / sp["windows"],
                 theta_curve=r["theta_curve"], train=r["train"], labelling_s=r["labelling_s"],
                 positives_per_window=r["positives_per_window"],
-                windows=dict(train=n_train, val=2048, test=2048))
+                windows=dict(train=n_train, val=2048, test=2048),
+                no_local_head=r.get("no_local_head"))
 
 
 def copy_calibration(nbytes: int = 256 << 20, reps: int = 5):
@@ -394,6 +396,8 @@ def main():
                          "('' for none)")
     ap.add_argument("--proposal-train", type=int, default=49152,
                     help="training windows of the learned proposal trained inside the run")
+    ap.add_argument("--proposal-compare-no-local", action="store_true",
+                    help="also train the proposal network without its local layer on the same windows")
     ap.add_argument("--batch-streams", type=int, default=512)
     ap.add_argument("--batch-precisions", default="bf16",
                     help="precisions of the batch runs with --workload none (comma-separated)")
@@ -422,7 +426,7 @@ def main():
             forms["batch"] = dict(workload=bw["desc"], runs=[run_batch(bw, p, max(1, args.steps), args.warmup)
                                                              for p in args.batch_precisions.split(",")])
         if "proposal" in forms_wanted:
-            forms["proposal"] = run_proposal(args.proposal_train, pool)
+            forms["proposal"] = run_proposal(args.proposal_train, pool, args.proposal_compare_no_local)
             pool.close()
         print(json.dumps({"forms": forms}), flush=True)
         return

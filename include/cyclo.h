@@ -411,11 +411,14 @@ int cyc_estimate_cycle_freqs(const void* d_x, int64_t n, double alpha0, int32_t 
  * W0[64][3][7], b0[64], W1[64][64][7], b1, W2, b2, W3, b3, Wh[1024][65536],
  * bh[1024], Wl[64].  flags: CYC_OP_FP32 or CYC_OP_BF16 operands for every
  * matrix product (FP32 accumulation, FP32 master weights and AdamW moments;
- * the local layer is FP32 in both).
+ * the local layer is FP32 in both), optionally | CYC_NN_NO_LOCAL: the network
+ * without the local layer (the four convolutions and the dense head alone; Wl
+ * stays in the parameter vector, is ignored and gets a zero gradient).
  * max_batch bounds n_windows of every call (activations are allocated at
  * creation).  All d_* pointers are device memory.  Errors: CYC_EINVAL,
  * CYC_EUNSUPPORTED (other precisions), CYC_ENOMEM, CYC_EDEVICE.
  */
+#define CYC_NN_NO_LOCAL 0x100u
 typedef struct cyc_model cyc_model;
 int64_t cyc_model_num_params(void);
 int cyc_model_create(cyc_model** out, int32_t max_batch, uint32_t flags, void* stream);

@@ -723,6 +723,7 @@ using namespace cyclo::nn;
 
 struct cyc_model {
   int prec = 0;  // 0: FP32 operands, 1: BF16 operands
+  bool local = true;  // the shared local head (CYC_NN_NO_LOCAL turns it off)
   int maxb = 0;
   int64_t np = 0;
   int64_t offW[NCONV], offb[NCONV], offWh = 0, offbh = 0, offWl = 0;
@@ -797,7 +798,9 @@ hipError_t model_forward(cyc_model* m, const float* feat, int n, hipStream_t st)
   hipError_t e = gemm(m->prec, false, true, m->hbuf, m->w + m->offWh, m->z, n, NOUT, HDIM, HDIM, HDIM, NOUT,
                       false, st, m->ws, m->ws_cap);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(local_head_kernel, dim3(nb(BL)), dim3(256), 0, st, m->a[NCONV - 1], m->w + m->offWl, m->z, n);
+  if (m->local)
+    hipLaunchKernelGGL(local_head_kernel, dim3(nb(BL)), dim3(256), 0, st, m->a[NCONV - 1], m->w + m->offWl, m->z,
+                       n);
   return hipGetLastError();
 }
 
@@ -820,11 +823,17 @@ hipError_t model_backward(cyc_model* m, const float* feat, const float* labels, 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(head_layout_kernel, dim3(nb((int64_t)n * HDIM)), dim3(256), 0, st, m->hbuf, m->da, n, 1);
   const int64_t BL = (int64_t)n * LEN;
-  // dWl[c] = sum_i dz[i] a[c][i]
-  hipLaunchKernelGGL(rowsum_part_kernel, dim3(CH, RSPLIT), dim3(256), 0, st, m->a[NCONV - 1], m->dz, m->rpart, BL);
-  hipLaunchKernelGGL(rowsum_final_kernel, dim3(1), dim3(CH), 0, st, m->rpart, m->g + m->offWl, CH);
-  hipLaunchKernelGGL(local_head_dgrad_kernel, dim3(nb((int64_t)CH * BL)), dim3(256), 0, st, m->da,
-                     m->w + m->offWl, m->dz, BL);
+  // dWl[c] = sum_i dz[i] a[c][i]; without the local head its gradient is 0 and
+  // it adds nothing to da
+  if (m->local) {
+    hipLaunchKernelGGL(rowsum_part_kernel, dim3(CH, RSPLIT), dim3(256), 0, st, m->a[NCONV - 1], m->dz, m->rpart, BL);
+    hipLaunchKernelGGL(rowsum_final_kernel, dim3(1), dim3(CH), 0, st, m->rpart, m->g + m->offWl, CH);
+    hipLaunchKernelGGL(local_head_dgrad_kernel, dim3(nb((int64_t)CH * BL)), dim3(256), 0, st, m->da,
+                       m->w + m->offWl, m->dz, BL);
+  } else {
+    const hipError_t e = cyclo::launch_zero(m->g + m->offWl, sizeof(float) * CH, st);
+    if (e != hipSuccess) return e;
+  }
   for (int i = NCONV - 1; i >= 0; --i) {
     const int cin = i == 0 ? CIN : CH;
     const float* in = i == 0 ? feat : m->a[i - 1];
@@ -866,12 +875,13 @@ int64_t cyc_model_num_params(void) { return model_nparams(); }
 
 int cyc_model_create(cyc_model** out, int32_t max_batch, uint32_t flags, void* stream) {
   if (!out || max_batch < 1 || max_batch > 4096) return CYC_EINVAL;
-  if (flags & ~CYC_OP_MASK) return CYC_EINVAL;
+  if (flags & ~(CYC_OP_MASK | CYC_NN_NO_LOCAL)) return CYC_EINVAL;
   const int prec = (int)(flags & CYC_OP_MASK);
   if (prec != 0 && prec != 1) return CYC_EUNSUPPORTED;
   cyc_model* m = new (std::nothrow) cyc_model();
   if (!m) return CYC_ENOMEM;
   m->prec = prec;
+  m->local = (flags & CYC_NN_NO_LOCAL) == 0;
   m->maxb = max_batch;
   int64_t o = 0, cin = CIN;
   for (int i = 0; i < NCONV; ++i) {

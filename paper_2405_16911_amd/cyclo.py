@@ -29,6 +29,7 @@ CYC_TW_SPLIT = 0x4
 CYC_OUT_C128 = 0x8
 CYC_TBL_R = 0x10
 CYC_TBL_RCONJ = 0x20
+CYC_NN_NO_LOCAL = 0x100
 
 #: exported symbols and their ctypes signatures (restype, argtypes)
 SIGNATURES = {

@@ -273,7 +273,13 @@ def dataset(model, fg: FullGrid, seed: int, first: int, n: int, keep_windows: bo
 
 
 def run(n_train=4096, n_val=512, n_test=512, epochs=30, batch=128, lr=2e-3, wd=0.1, seed=5,
-        target_miss=0.01, log=print, pool=None, augment=True):
+        target_miss=0.01, log=print, pool=None, augment=True, compare_no_local=False):
+    """Labels, trains and evaluates the proposal network (see the module docstring).
+
+    compare_no_local: also train the network without its local layer
+    (CYC_NN_NO_LOCAL: the four convolutions and the dense head alone) on the
+    same windows, and report its miss rates at its own validated threshold.
+    """
     import torch
     t0 = time.time()
     res = {"config": dict(n_train=n_train, n_val=n_val, n_test=n_test, epochs=epochs, batch=batch, lr=lr,
@@ -321,6 +327,23 @@ def run(n_train=4096, n_val=512, n_test=512, epochs=30, batch=128, lr=2e-3, wd=0
                            selected_bins_per_window=float(sel.float().sum(1).mean().item()))
         log(f"{name}: miss {mr:.4f} (no fallback {mr0:.4f}), fallback {evals[name]['fallback_rate']:.3f}")
     res["eval"] = evals
+    if compare_no_local:
+        m2 = cyclo.ProposalModel(max(batch, 512), cyclo.CYC_OP_BF16 | cyclo.CYC_NN_NO_LOCAL)
+        m2.set_params(init_params(seed))
+        t3 = time.time()
+        tr2 = train(m2, f_tr, ls_tr, epochs, batch, lr, wd, seed, log, val=(f_va, l_va), augment=augment)
+        sel_v2, conf_v2 = cyclo.cyc_select(probabilities(m2, f_va, 512), 16, 2, ZERO_BIN)
+        theta2 = choose_theta(conf_v2, sel_v2, l_va, target_miss)
+        sel2, conf2 = cyclo.cyc_select(probabilities(m2, f_te, 512).contiguous(), 16, 2, ZERO_BIN)
+        fb2 = conf2 < theta2
+        mr2, _, _ = miss_rate(sel2, l_te, fb2)
+        mr20, _, _ = miss_rate(sel2, l_te, torch.zeros_like(fb2))
+        res["no_local_head"] = dict(theta=theta2, miss_rate=mr2, miss_rate_without_fallback=mr20,
+                                    fallback_rate=float(fb2.float().mean().item()),
+                                    train_s=time.time() - t3, val_loss_best=min(tr2["val_losses"]))
+        log(f"without the local layer: miss {mr2:.4f} (no fallback {mr20:.4f}), "
+            f"fallback {res['no_local_head']['fallback_rate']:.3f}")
+        m2.close()
     prob = probabilities(model, f_te, 512)
     sel, conf = cyclo.cyc_select(prob.contiguous(), 16, 2, ZERO_BIN)
     thetas = [0.0, 0.5, 0.8, 0.9, 0.95, 0.98, 0.99, 0.995, 0.999, 1.0]

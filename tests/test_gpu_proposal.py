@@ -286,3 +286,28 @@ def test_propose_equals_its_steps_and_the_oracle_selection(cy):
         s_ref, c_ref = P.select(prob[i].astype(np.float64), k=16, width=2, zero_bin=512)
         assert list(want) == list(s_ref)
         assert abs(conf[i] - c_ref) < 1e-6
+
+
+def test_network_without_local_layer(cy):
+    """CYC_NN_NO_LOCAL: the four convolutions and the dense head alone (the
+    oracle's network with Wl = 0); Wl is ignored and gets a zero gradient."""
+    p = _params(8)
+    rng = np.random.default_rng(9)
+    B = 2
+    X = rng.standard_normal((B, 3, 1024)).astype(np.float32).astype(np.float64)
+    y = (rng.random((B, 1024)) < 0.05).astype(np.float64)
+    p0 = dict(p, Wl=np.zeros_like(p["Wl"]))
+    z, cache = P.forward(p0, X)
+    g = P.backward(p0, cache, z, y)
+    m = cy.ProposalModel(B, cy.CYC_OP_FP32 | cy.CYC_NN_NO_LOCAL)
+    m.set_params(_flat(p))                   # Wl nonzero on the GPU: must be ignored
+    feat = torch.from_numpy(np.ascontiguousarray(X.transpose(1, 0, 2)).astype(np.float32)).to("cuda")
+    prob = m.forward(feat).cpu().numpy().astype(np.float64)
+    gg, _ = m.gradients(feat, torch.from_numpy(y.astype(np.float32)).to("cuda"))
+    gg = _unflat(gg.cpu().numpy().astype(np.float64), p)
+    m.close()
+    assert _rel(prob, P.sigmoid(z)) <= 1e-5
+    assert not np.any(gg["Wl"])
+    for k in KEYS:
+        if k != "Wl":
+            assert _rel(gg[k], g[k]) <= 2e-5, k
