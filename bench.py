@@ -351,7 +351,9 @@ def run_proposal(n_train: int, pool, compare_no_local: bool = False):
                 full_grid_kernel_tflops=sp["full_grid_kernel_tflops"],
                 full_grid_kernel_frac=sp["full_grid_kernel_tflops"] / PEAK_TFLOPS["bf16"],
                 network="4 circular conv1d (64 ch, k 7) + dense 65536->1024 head + a shared local head "
-                        "(64 weights; added to the specified network, see DESIGN reading 17)",
+                        "(64 weights shared by all coarse bins; a deviation from the specified network, which "
+                        "has no local head: it lets every bin learn from the spectral lines of all bins at "
+                        "small training sizes)",
                 miss_rate_no_fallback=ev["trained"]["miss_rate_without_fallback"],
                 miss_rate_untrained=ev["untrained"]["miss_rate_without_fallback"],
                 miss_rate_heuristic=ev["heuristic"]["miss_rate_without_fallback"],
