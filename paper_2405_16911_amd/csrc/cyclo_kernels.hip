@@ -71,6 +71,14 @@ struct Op<PREC_BF16> {
     return __builtin_bit_cast(uint32_t, v);
   }
   static __device__ __forceinline__ float rnd(float a) { return (float)(__bf16)a; }
+  // The two Hankel words of one sample, (re, -im) and (im, re), one packed
+  // conversion each (the same rounding as pack).  Written out because the
+  // compiler otherwise converts each part once and assembles both words with
+  // sign flips and byte permutes, three times the instructions.
+  static __device__ __forceinline__ void hankel(float2 v, uint32_t& w0, uint32_t& w1) {
+    asm("v_cvt_pk_bf16_f32 %0, %1, -%2" : "=v"(w0) : "v"(v.x), "v"(v.y));
+    asm("v_cvt_pk_bf16_f32 %0, %1, %2" : "=v"(w1) : "v"(v.y), "v"(v.x));
+  }
   static __device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(e8, a),
                                                   __builtin_bit_cast(e8, b), c, 0, 0, 0);
@@ -95,6 +103,10 @@ struct Op<PREC_F16> {
   static __device__ __forceinline__ float rnd(float a) {
     asm volatile("" : "+v"(a));
     return (float)(_Float16)a;
+  }
+  static __device__ __forceinline__ void hankel(float2 v, uint32_t& w0, uint32_t& w1) {
+    w0 = pack(v.x, -v.y);
+    w1 = pack(v.y, v.x);
   }
   static __device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(e8, a),
@@ -389,12 +401,7 @@ __device__ __forceinline__ void contract_f32_tile(const ContractArgs& a, TileId 
 // K block.  The Hankel operand is kept as eight copies (cr, sh) holding the
 // pairs (re, -im) (cr = 0) or (im, re) (cr = 1) of the window shifted by
 // sh = 0..3 samples, so every 16-byte fragment read is aligned for any lag.
-// Copy (cr, sh) starts at word cr*CO + sh*ZP with ZP = 8 (mod 64) and
-// CO = 4 ZP (= 32 mod 64).  A 16-byte fragment read is served sixteen lanes at
-// a time from 64 four-byte banks; the sixteen lanes of a group read copies
-// (cr, sh) at fragment offsets 0 and +4 words, i.e. in 16-byte bank units
-// 8 cr + 2 sh + {0, 1} (mod 16): all sixteen units differ, so the reads are
-// free of bank conflicts.
+// Copy (cr, sh) starts at word cr*CO + sh*ZP (ZP and CO below).
 template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS, int SCHED, int TBL>
 __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId tid_in) {
   using O = Op<PREC>;
@@ -406,8 +413,12 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
   constexpr int G = KS * AW / NT;
   static_assert(G >= 4 && G * NT == KS * AW && KS % G == 0 && G % 4 == 0, "B-gen split");
   constexpr int ZW = KS + TW;                    // entries per shifted copy (multiple of 4)
-  constexpr int ZP = ((ZW + 55) / 64) * 64 + 8;  // copy pitch >= ZW, = 8 (mod 64)
-  constexpr int CO = 4 * ZP;                     // offset of the cr = 1 copies, = 32 (mod 64)
+  // Copy pitch ZP >= ZW with ZP = 8 (mod 64) words and the cr = 1 copies at
+  // CO = 4 ZP.  (A probe of the fragment reads alone found ZP = 32, CO = 16
+  // (mod 64) free of the 2-way bank conflicts this layout has, but the kernels
+  // ran 0-4% slower with it: its Hankel-copy writes conflict instead.)
+  constexpr int ZP = ((ZW + 55) / 64) * 64 + 8;
+  constexpr int CO = 4 * ZP;
   constexpr int ZS = CO + 4 * ZP;                // words per buffer
   static_assert(ZP >= ZW && ZP % 64 == 8 && CO % 64 == 32, "Hankel copy layout");
   constexpr int XW = ZW + 4;                     // staged Hankel samples (ZW + 3 are read)
@@ -465,9 +476,7 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
       uint32_t w0[4], w1[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const float2 v = Xh[buf][4 * grp + sh + k];
-        w0[k] = O::pack(v.x, -v.y);
-        w1[k] = O::pack(v.y, v.x);
+        O::hankel(Xh[buf][4 * grp + sh + k], w0[k], w1[k]);
       }
       *reinterpret_cast<uint4*>(&Zs[buf][sh * ZP + 4 * grp]) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
       *reinterpret_cast<uint4*>(&Zs[buf][CO + sh * ZP + 4 * grp]) =
@@ -545,30 +554,50 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
     }
   };
 
+  // A step's twiddle entries wait in LDS between their load and their use,
+  // in the padding words of the B rows (the matrix-core reads stop at word
+  // KS): row ga for the thread's cycle frequency, row AW + ga for the second
+  // one of a one-table tile.  One thread per cycle frequency writes them.
+  auto put_h = [&](int buf, const Stager<NT, XW, KS>& st) {
+    if (gj == 0) {
+      *reinterpret_cast<float2*>(&Bs[buf][0][ga][KS]) = st.hv;
+      if (TBL) *reinterpret_cast<float2*>(&Bs[buf][0][AW + ga][KS]) = st.hv2;
+    }
+  };
+  auto get_h = [&](int buf, int row0) { return *reinterpret_cast<const float2*>(&Bs[buf][0][row0 + ga][KS]); };
+  // Sample loads run two K steps ahead: the registers of two stagers
+  // alternate, so a load has a whole step (its matrix-core work and operand
+  // generation) more to land than it would with one stager, which a short
+  // step (64 lags) does not cover at load latencies under full load.
   if (ns > 0) {
-    Stager<NT, XW, KS> stg;
-    stg.load(a.v, a.vy, tl.cbase, tl.tau0, tl.yend, hptr(0), tid, hptr2(0));
-    stg.store(&Xh[0][0], &Xy[0][0], tid);
-    const float2 h0 = stg.hv, h02 = stg.hv2;
-    stg.load(a.v, a.vy, tl.cbase + KS, tl.tau0, tl.yend, hptr(1), tid, hptr2(1));
-    stg.store(&Xh[1][0], &Xy[1][0], tid);
-    float2 hnext = stg.hv, hnext2 = stg.hv2;
+    Stager<NT, XW, KS> sa, sb;
+    sa.load(a.v, a.vy, tl.cbase, tl.tau0, tl.yend, hptr(0), tid, hptr2(0));
+    sa.store(&Xh[0][0], &Xy[0][0], tid);
+    const float2 h0 = sa.hv, h02 = sa.hv2;
+    sb.load(a.v, a.vy, tl.cbase + KS, tl.tau0, tl.yend, hptr(1), tid, hptr2(1));
+    sb.store(&Xh[1][0], &Xy[1][0], tid);
+    put_h(1, sb);
+    sa.load(a.v, a.vy, tl.cbase + 2 * KS, tl.tau0, tl.yend, hptr(2), tid, hptr2(2));
     __syncthreads();
     produce(0, h0, h02);
     __syncthreads();
-    for (int ks = 0; ks + 1 < ns; ++ks) {
+    // Step ks: cur holds the loads of step ks + 2, which go to LDS at the end
+    // of the step (the thread's twiddle entry too, to its own slot), and nxt
+    // takes those of step ks + 3.  No loaded register is carried past the
+    // two-step unrolled loop body, so none needs a copy, and a wait for the
+    // load, at the back edge.
+    auto body = [&](int ks, Stager<NT, XW, KS>& cur, Stager<NT, XW, KS>& nxt) {
       const int buf = ks & 1;
-      stg.load(a.v, a.vy, tl.cbase + (int64_t)(ks + 2) * KS, tl.tau0, tl.yend, hptr(ks + 2), tid,
-               hptr2(ks + 2));
+      nxt.load(a.v, a.vy, tl.cbase + (int64_t)(ks + 3) * KS, tl.tau0, tl.yend, hptr(ks + 3), tid,
+               hptr2(ks + 3));
       // The wave issuing matrix-core work runs at raised priority; the other
       // resident wave's operand generation fills the issue slots it leaves.
       __builtin_amdgcn_s_setprio(1);
       mfma_step(buf);
       __builtin_amdgcn_s_setprio(0);
-      produce(buf ^ 1, hnext, hnext2);
-      stg.store(&Xh[buf][0], &Xy[buf][0], tid);
-      hnext = stg.hv;
-      hnext2 = stg.hv2;
+      produce(buf ^ 1, get_h(buf ^ 1, 0), get_h(buf ^ 1, TBL ? AW : 0));
+      cur.store(&Xh[buf][0], &Xy[buf][0], tid);
+      put_h(buf, cur);
       if (SCHED) {
         // Interleave the next step's operand generation with this step's
         // matrix-core instructions so one wave overlaps both.
@@ -583,7 +612,13 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
         }
       }
       __syncthreads();
+    };
+    int ks = 0;
+    for (; ks + 2 < ns; ks += 2) {
+      body(ks, sa, sb);
+      body(ks + 1, sb, sa);
     }
+    if (ks + 1 < ns) body(ks, sa, sb);
     mfma_step((ns - 1) & 1);
   }
   store_tiles<WM, WN, AW, TBL>(a, tl.id, tl.tau0, tl.alpha0, wm, wn, lane, acc);
@@ -681,7 +716,7 @@ __global__ __launch_bounds__(64, 1) void contract_rg(ContractArgs a) {
   static_assert(KS % 8 == 0, "shape");
   constexpr int NKB = KS / 8;                    // 8-sample K blocks per step
   constexpr int ZW = KS + TW;
-  constexpr int ZP = ((ZW + 55) / 64) * 64 + 8;  // see contract_16
+  constexpr int ZP = ((ZW + 55) / 64) * 64 + 8;  // layout of contract_16_tile
   constexpr int CO = 4 * ZP;
   constexpr int ZS = CO + 4 * ZP;
   constexpr int XW = ZW + 4;
@@ -732,9 +767,7 @@ __global__ __launch_bounds__(64, 1) void contract_rg(ContractArgs a) {
       uint32_t w0[4], w1[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const float2 v = Xh[xbuf][4 * grp + sh + k];
-        w0[k] = O::pack(v.x, -v.y);
-        w1[k] = O::pack(v.y, v.x);
+        O::hankel(Xh[xbuf][4 * grp + sh + k], w0[k], w1[k]);
       }
       *reinterpret_cast<uint4*>(&Zs[buf][sh * ZP + 4 * grp]) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
       *reinterpret_cast<uint4*>(&Zs[buf][CO + sh * ZP + 4 * grp]) =
@@ -886,6 +919,216 @@ hipError_t launch_rg(const ContractArgs& a, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ----------------------------------------------------------------------------- register-B contraction, shared Hankel copies
+//
+// BF16/FP16 tile of TW = 16 RB lags and NW blocks of 32 cycle frequencies, one
+// block per wave.  Each wave generates the modulated operands of its own
+// cycle frequencies (both tables) directly in the registers of the
+// matrix-core B fragments, so they never pass through LDS; the Hankel copies
+// are built once per workgroup and step by all threads and shared by the
+// waves, so LDS carries only the sample window, the copies and their
+// fragment reads.  Same operands and K order as contract_16_tile, so the
+// tables are bit-identical.  One barrier per K step.
+template <int PREC, int SPLIT, int RB, int NW, int KS, int IL>
+__device__ __forceinline__ void contract_16r_tile(const ContractArgs& a, TileId tid_in) {
+  using O = Op<PREC>;
+  constexpr int NT = 64 * NW;
+  constexpr int TW = 16 * RB, AW = 32 * NW;
+  static_assert(KS % 8 == 0, "shape");
+  constexpr int NKB = KS / 8;                    // 8-sample K blocks per step
+  constexpr int ZW = KS + TW;
+  constexpr int ZP = ((ZW + 55) / 64) * 64 + 8;  // layout of contract_16_tile
+  constexpr int CO = 4 * ZP;
+  constexpr int ZS = CO + 4 * ZP;
+  constexpr int XW = ZW + 4;
+  constexpr int ZU = ZW;
+  constexpr int ZR = (ZU + NT - 1) / NT;
+  constexpr int NB = SPLIT ? 2 : 1;
+
+  __shared__ __attribute__((aligned(16))) uint32_t Zs[2][ZS];
+  __shared__ __attribute__((aligned(16))) float2 Xh[2][XW];
+  __shared__ __attribute__((aligned(16))) float2 Xy[3][KS];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int h = lane >> 5, l32 = lane & 31;
+  const Tile tl(a, tid_in, TW, AW, KS);
+  const int ns = tl.ns;
+
+  // the lane's cycle frequency and the chunk-relative twiddles of the samples
+  // it modulates: j = 8 kb + 4 h + g within a step
+  const int al = tl.alpha0 + 32 * w + l32;
+  const bool aok = al < a.A;
+  float2 lo[NKB][4];
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+      lo[kb][g] = aok ? a.Lo[(int64_t)al * KS + 8 * kb + 4 * h + g] : make_float2(0.f, 0.f);
+  const float2* Hrow = a.H + (int64_t)(aok ? al : 0) * tl.nsteps;
+  auto hptr = [&](int ks) { return Hrow + min(ks, tl.nsteps - 1); };
+
+  // Hankel fragment of row block rb at K block kb: word zoff0 + 16 rb + 8 kb
+  int zoff0;
+  {
+    const int p0 = (l32 >> 1) + 4 * h;
+    const int sh = p0 & 3;
+    zoff0 = (l32 & 1) * CO + sh * ZP + (p0 - sh);
+  }
+
+  auto build_hankel = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < ZR; ++i) {
+      const int u = (tid + i * NT) % ZU;
+      const int grp = u >> 2, sh = u & 3;
+      uint32_t w0[4], w1[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        O::hankel(Xh[buf][4 * grp + sh + k], w0[k], w1[k]);
+      }
+      *reinterpret_cast<uint4*>(&Zs[buf][sh * ZP + 4 * grp]) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
+      *reinterpret_cast<uint4*>(&Zs[buf][CO + sh * ZP + 4 * grp]) =
+          make_uint4(w1[0], w1[1], w1[2], w1[3]);
+    }
+  };
+
+  // modulated fragments of one K block: [b][0] table R (Y), [b][1] table Rc (Yc)
+  typedef uint4 BFrag[NB][2];
+  auto gen_b = [&](int buf, int kb, float2 hv, BFrag& f) {
+    const float4 xa = *reinterpret_cast<const float4*>(&Xy[buf][8 * kb + 4 * h]);
+    const float4 xb = *reinterpret_cast<const float4*>(&Xy[buf][8 * kb + 4 * h + 2]);
+    const float2 xs[4] = {make_float2(xa.x, xa.y), make_float2(xa.z, xa.w), make_float2(xb.x, xb.y),
+                          make_float2(xb.z, xb.w)};
+    float2 y[4], yc[4];
+    modulate<4>(xs, hv, lo[kb], y, yc);
+    uint32_t py[NB][4], pyc[NB][4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      py[0][g] = O::pack(y[g].x, y[g].y);
+      pyc[0][g] = O::pack(yc[g].x, yc[g].y);
+      if (SPLIT) {
+        py[NB - 1][g] = O::pack(y[g].x - O::rnd(y[g].x), y[g].y - O::rnd(y[g].y));
+        pyc[NB - 1][g] = O::pack(yc[g].x - O::rnd(yc[g].x), yc[g].y - O::rnd(yc[g].y));
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      f[b][0] = make_uint4(py[b][0], py[b][1], py[b][2], py[b][3]);
+      f[b][1] = make_uint4(pyc[b][0], pyc[b][1], pyc[b][2], pyc[b][3]);
+    }
+  };
+
+  f32x16 acc[RB][2];
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][k][v] = 0.f;
+
+  // Software pipeline over K blocks: the fragments of the next block (the
+  // first block of the next step at a step's end) are generated while the
+  // current block's matrix-core instructions run, in two register sets that
+  // alternate (NKB is even, so every step starts in set 0).  Hankel fragment
+  // (rb, kb) equals (rb + 1, kb - 2), so a step reads its 2 (RB - 1) + NKB
+  // distinct ones once.  The samples a lane modulates are read from a
+  // triple-buffered Xy: a wave may still read step ks's samples while
+  // another writes step ks + 2's.
+  static_assert(NKB % 2 == 0, "two fragment sets");
+  if (ns > 0) {
+    Stager<NT, XW, KS> stg;
+    stg.load(a.v, a.vy, tl.cbase, tl.tau0, tl.yend, hptr(0), tid);
+    stg.store(&Xh[0][0], &Xy[0][0], tid);
+    float2 hcur = stg.hv;
+    stg.load(a.v, a.vy, tl.cbase + KS, tl.tau0, tl.yend, hptr(1), tid);
+    stg.store(&Xh[1][0], &Xy[1][0], tid);
+    float2 hnext = stg.hv;
+    __syncthreads();
+    build_hankel(0);
+    BFrag bf[2];
+    gen_b(0, 0, hcur, bf[0]);
+    __syncthreads();
+    int y0 = 0;  // = ks % 3
+    for (int ks = 0; ks < ns; ++ks) {
+      const int zb = ks & 1;
+      const int y1 = y0 == 2 ? 0 : y0 + 1, y2 = y1 == 2 ? 0 : y1 + 1;
+      const bool more = ks + 1 < ns;
+      if (more)
+        stg.load(a.v, a.vy, tl.cbase + (int64_t)(ks + 2) * KS, tl.tau0, tl.yend, hptr(ks + 2), tid);
+      const uint32_t* zp = &Zs[zb][0] + zoff0;
+      constexpr int NAF = 2 * (RB - 1) + NKB;
+      uint4 af[NAF];
+#pragma unroll
+      for (int o = 0; o < NAF; ++o) af[o] = *reinterpret_cast<const uint4*>(zp + 8 * o);
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) {
+        BFrag& cur = bf[kb & 1];
+        BFrag& nxt = bf[(kb & 1) ^ 1];
+        if (kb + 1 < NKB)
+          gen_b(y0, kb + 1, hcur, nxt);
+        else if (more)
+          gen_b(y1, 0, hnext, nxt);
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            acc[rb][0] = O::mfma(af[2 * rb + kb], cur[b][0], acc[rb][0]);
+            acc[rb][1] = O::mfma(af[2 * rb + kb], cur[b][1], acc[rb][1]);
+          }
+      }
+      if (IL) {
+        constexpr int NMF = NKB * RB * 2 * NB;
+#pragma unroll
+        for (int i = 0; i < NMF; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+          __builtin_amdgcn_sched_group_barrier(0x002, IL, 0);  // VALU
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+        }
+      }
+      if (more) {
+        build_hankel(zb ^ 1);                    // step ks + 1 from Xh[zb ^ 1]
+        stg.store(&Xh[zb][0], &Xy[y2][0], tid);  // step ks + 2
+        hcur = hnext;
+        hnext = stg.hv;
+        __syncthreads();
+      }
+      y0 = y1;
+    }
+  }
+  store_tiles<RB, 2, 32, 0>(a, tl.id, tl.tau0, tl.alpha0 + 32 * w, 0, 0, lane, acc);
+}
+
+template <int PREC, int SPLIT, int RB, int NW, int KS, int IL>
+__global__ __launch_bounds__(64 * NW, RB > 4 ? 1 : 2) void contract_16r(ContractArgs a) {
+  contract_16r_tile<PREC, SPLIT, RB, NW, KS, IL>(a, tile_of(a));
+}
+
+template <int PREC, int SPLIT, int RB, int NW, int KS, int IL>
+__global__ __launch_bounds__(64 * NW, RB > 4 ? 1 : 2) void contract_16r_batch(BatchArgs b) {
+  for (;;) {
+    const int it = next_item(b.counter);
+    if (it >= *b.n_items) break;
+    const BItem bi = b.items[it];
+    const BJob j = b.jobs[bi.job];
+    TileId id;
+    id.chunk = 0;
+    id.tt = bi.tt;
+    id.at = bi.at;
+    contract_16r_tile<PREC, SPLIT, RB, NW, KS, IL>(job_args(b, j), id);
+  }
+}
+
+template <int PREC, int SPLIT, int RB, int NW, int KS, int IL>
+hipError_t launch_16r(const ContractArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((contract_16r<PREC, SPLIT, RB, NW, KS, IL>), dim3(grid), dim3(64 * NW), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int PREC, int SPLIT, int RB, int NW, int KS, int IL>
+hipError_t launch_16r_batch(const BatchArgs& b, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((contract_16r_batch<PREC, SPLIT, RB, NW, KS, IL>), dim3(grid), dim3(64 * NW), 0, st, b);
+  return hipGetLastError();
+}
+
 // ----------------------------------------------------------------------------- config table
 
 template <int TW, int AW, int WAVES_M, int WAVES_N, int KS, int TBL = 0>
@@ -927,6 +1170,10 @@ template <int TW, int AW, int WAVES_M, int WAVES_N, int KS>
 int grid_f32_batch() {
   return resident_grid(contract_f32_batch<TW, AW, WAVES_M, WAVES_N, KS>, 64 * WAVES_M * WAVES_N);
 }
+template <int PREC, int SPLIT, int RB, int NW, int KS, int IL>
+int grid_16r_batch() {
+  return resident_grid(contract_16r_batch<PREC, SPLIT, RB, NW, KS, IL>, 64 * NW);
+}
 template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS, int SCHED>
 int grid_16_batch() {
   return resident_grid(contract_16_batch<PREC, SPLIT, TW, AW, WAVES_M, WAVES_N, KS, SCHED>,
@@ -966,6 +1213,16 @@ int grid_16_batch() {
   CFG_16_T(PREC_F16, "f16", 0, TW, AW, WMW, WNW, 32, 0, TBL, TN),                   \
   CFG_16_T(PREC_F16, "f16", 1, TW, AW, WMW, WNW, 32, 0, TBL, TN)
 
+#define CFG_16R(P, PN, SP, RB, NW, KS, IL)                                              \
+  {P, SP, 16 * RB, 32 * NW, KS, 64 * NW, &launch_16r<P, SP, RB, NW, KS, IL>,                \
+   PN "_s" #SP "_t" #RB "x16_a" #NW "x32_regsh_k" #KS "_i" #IL,                             \
+   &launch_16r_batch<P, SP, RB, NW, KS, IL>, &grid_16r_batch<P, SP, RB, NW, KS, IL>, 0}
+#define CFG_16R_ALL(RB, NW, KS, IL)                 \
+  CFG_16R(PREC_BF16, "bf16", 0, RB, NW, KS, IL),    \
+  CFG_16R(PREC_BF16, "bf16", 1, RB, NW, KS, IL),    \
+  CFG_16R(PREC_F16, "f16", 0, RB, NW, KS, IL),      \
+  CFG_16R(PREC_F16, "f16", 1, RB, NW, KS, IL)
+
 #define CFG_RG_ALL(RB, NA, KS)                  \
   CFG_RG(PREC_BF16, "bf16", 0, RB, NA, KS),     \
   CFG_RG(PREC_BF16, "bf16", 1, RB, NA, KS),     \
@@ -989,6 +1246,10 @@ static const KernelCfg g_cfgs[] = {
     CFG_16_ALL(128, 128, 2, 2, 32, 1),
     CFG_16_ALL(64, 64, 2, 2, 32, 0),
     CFG_RG_ALL(8, 1, 32),
+    CFG_16R_ALL(4, 4, 32, 6),
+    CFG_16R_ALL(4, 4, 32, 0),
+    CFG_16R_ALL(4, 2, 32, 0),
+    CFG_16R_ALL(8, 4, 32, 0),
     CFG_16_ALL(128, 64, 2, 2, 32, 1),
     CFG_16_ALL(128, 64, 2, 2, 32, 0),
     CFG_16_ALL(64, 64, 2, 2, 32, 8),

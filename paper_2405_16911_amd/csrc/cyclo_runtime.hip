@@ -173,6 +173,12 @@ int pick_cfg(int prec, int split, int tbl, int T, int A) {
     }
   }
   const int want_tw = T > 64 ? 128 : (T > 32 ? 64 : 32);
+  // 16-bit operands at 33..64 lags: the register-operand tile with shared
+  // Hankel copies (the fastest measured there)
+  if (prec != PREC_F32 && want_tw == 64)
+    for (int i = 0; i < n; ++i)
+      if (mode_ok(i) && c[i].tw == 64 && c[i].aw == 128 && c[i].nthreads == 256 && std::strstr(c[i].name, "regsh"))
+        return i;
   int best = -1;
   for (int i = 0; i < n; ++i) {
     if (!mode_ok(i) || c[i].tw != want_tw || c[i].aw != 64) continue;
