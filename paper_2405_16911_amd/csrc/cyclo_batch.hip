@@ -197,6 +197,7 @@ BatchArgs batch_args(cyc_batch* b) {
   a.counter = &b->d_cnt()->counter;
   a.T = b->T;
   a.Kc = b->Kc;
+  a.hs = (int)b->aoff.back();
   return a;
 }
 
@@ -510,7 +511,7 @@ int cyc_batch_push(cyc_batch* b, const void* const* d_x, const int64_t* n, void*
       j.n_prod = b->Kc;
       j.abs_base = b->nc[s] + c * b->Kc;
       j.alpha_r = b->alpha_r + b->aoff[s];
-      j.H = b->H + b->aoff[s] * b->nsteps;
+      j.H = b->H + b->aoff[s];
       j.Lo = b->Lo + b->aoff[s] * b->KS;
       j.part = b->part + r.part_used;
       j.E = b->E + r.E_used;
@@ -608,7 +609,7 @@ int cyc_batch_read(cyc_batch* b, void* const* d_R, void* const* d_Rc, int64_t* n
       j.n_prod = m;
       j.abs_base = b->nc[s];
       j.alpha_r = b->alpha_r + b->aoff[s];
-      j.H = b->H + b->aoff[s] * b->nsteps;
+      j.H = b->H + b->aoff[s];
       j.Lo = b->Lo + b->aoff[s] * b->KS;
       j.part = b->part + r.part_used;
       j.E = b->E + r.E_used;

@@ -19,7 +19,7 @@ struct VSrc {
 //   part[c][0][t][a] = sum_{l < m_c} x[b_c+l+t] conj(x[b_c+l]) W[l][a]
 //   part[c][1][t][a] = sum_{l < m_c} x[b_c+l+t]      x[b_c+l]  W[l][a]
 // with b_c = v_off + c*Kc (virtual index), m_c = min(Kc, n_prod - c*Kc) and
-// the chunk-relative twiddle W[l][a] = H[a][l / KS] * Lo[a][l % KS]
+// the chunk-relative twiddle W[l][a] = H[l / KS][a] * Lo[a][l % KS]
 //                                  = exp(-j 2 pi frac(alpha_a l)).
 struct ContractArgs {
   VSrc v;   // Hankel (leading) samples: product i, lag t reads v[i + t]
@@ -28,9 +28,10 @@ struct ContractArgs {
   int64_t n_prod;
   int T, A, Kc;
   int n_tt, n_at, n_chunks;
-  const float2* H;   // [A][Kc/KS]
+  const float2* H;   // [Kc/KS][hs]: step s of cycle frequency a at H[s * hs + a]
   const float2* Lo;  // [A][KS]
   float2* part;      // [n_chunks][2][T][A]
+  int hs;            // row stride of H (>= A)
 };
 
 enum { PREC_F32 = 0, PREC_BF16 = 1, PREC_F16 = 2 };
@@ -87,6 +88,7 @@ struct BatchArgs {
   const int* n_items;
   int* counter;
   int T, Kc;
+  int hs;  // row stride of the twiddle table H (all streams' cycle frequencies)
 };
 
 typedef hipError_t (*BatchLaunch)(const BatchArgs&, int grid, hipStream_t);

@@ -296,8 +296,8 @@ __device__ __forceinline__ void contract_f32_tile(const ContractArgs& a, TileId 
 #pragma unroll
   for (int g = 0; g < G; ++g)
     lo[g] = aval ? a.Lo[(int64_t)galpha * KS + gj + g] : make_float2(0.f, 0.f);
-  const float2* Hrow = a.H + (int64_t)(aval ? galpha : 0) * tl.nsteps;
-  auto hptr = [&](int ks) { return Hrow + min(ks, tl.nsteps - 1); };
+  const float2* Hcol = a.H + (aval ? galpha : 0);
+  auto hptr = [&](int ks) { return Hcol + (int64_t)min(ks, tl.nsteps - 1) * a.hs; };
   // one table: the thread's second cycle frequency (tile column AW + ga)
   const int galpha2 = galpha + AW;
   const bool aval2 = TBL && galpha2 < a.A;
@@ -305,8 +305,10 @@ __device__ __forceinline__ void contract_f32_tile(const ContractArgs& a, TileId 
 #pragma unroll
   for (int g = 0; g < (TBL ? G : 1); ++g)
     lo2[g] = aval2 ? a.Lo[(int64_t)galpha2 * KS + gj + g] : make_float2(0.f, 0.f);
-  const float2* Hrow2 = a.H + (int64_t)(aval2 ? galpha2 : 0) * tl.nsteps;
-  auto hptr2 = [&](int ks) { return TBL ? Hrow2 + min(ks, tl.nsteps - 1) : (const float2*)nullptr; };
+  const float2* Hcol2 = a.H + (aval2 ? galpha2 : 0);
+  auto hptr2 = [&](int ks) {
+    return TBL ? Hcol2 + (int64_t)min(ks, tl.nsteps - 1) * a.hs : (const float2*)nullptr;
+  };
 
   int xoff[WM];
   uint32_t xneg[WM];
@@ -444,8 +446,8 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
   float2 lo[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) lo[g] = aval ? a.Lo[(int64_t)galpha * KS + gj + g] : make_float2(0.f, 0.f);
-  const float2* Hrow = a.H + (int64_t)(aval ? galpha : 0) * tl.nsteps;
-  auto hptr = [&](int ks) { return Hrow + min(ks, tl.nsteps - 1); };
+  const float2* Hcol = a.H + (aval ? galpha : 0);
+  auto hptr = [&](int ks) { return Hcol + (int64_t)min(ks, tl.nsteps - 1) * a.hs; };
   // one table: the thread's second cycle frequency (tile column AW + ga)
   const int galpha2 = galpha + AW;
   const bool aval2 = TBL && galpha2 < a.A;
@@ -453,8 +455,10 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
 #pragma unroll
   for (int g = 0; g < (TBL ? G : 1); ++g)
     lo2[g] = aval2 ? a.Lo[(int64_t)galpha2 * KS + gj + g] : make_float2(0.f, 0.f);
-  const float2* Hrow2 = a.H + (int64_t)(aval2 ? galpha2 : 0) * tl.nsteps;
-  auto hptr2 = [&](int ks) { return TBL ? Hrow2 + min(ks, tl.nsteps - 1) : (const float2*)nullptr; };
+  const float2* Hcol2 = a.H + (aval2 ? galpha2 : 0);
+  auto hptr2 = [&](int ks) {
+    return TBL ? Hcol2 + (int64_t)min(ks, tl.nsteps - 1) * a.hs : (const float2*)nullptr;
+  };
 
   // Word offset of this lane's Hankel fragment for the wave's first row block
   // (row R = 2 lag + cr, four samples from lag + 4h, in copy (cr, lag + 4h mod 4)).
@@ -663,6 +667,7 @@ __device__ __forceinline__ ContractArgs job_args(const BatchArgs& b, const BJob&
   a.n_at = 1;
   a.n_chunks = 1;
   a.H = j.H;
+  a.hs = b.hs;
   a.Lo = j.Lo;
   a.part = j.part;
   return a;
@@ -746,9 +751,9 @@ __global__ __launch_bounds__(64, 1) void contract_rg(ContractArgs a) {
 #pragma unroll
       for (int g = 0; g < 4; ++g)
         lo[nb][kb][g] = ok ? a.Lo[(int64_t)al * KS + 8 * kb + 4 * h + g] : make_float2(0.f, 0.f);
-    Hrow[nb] = a.H + (int64_t)(ok ? al : 0) * tl.nsteps;
+    Hrow[nb] = a.H + (ok ? al : 0);
   }
-  auto hidx = [&](int ks) { return min(ks, tl.nsteps - 1); };
+  auto hidx = [&](int ks) { return (int64_t)min(ks, tl.nsteps - 1) * a.hs; };
 
   int zoff[RB];
 #pragma unroll
@@ -964,8 +969,8 @@ __device__ __forceinline__ void contract_16r_tile(const ContractArgs& a, TileId 
 #pragma unroll
     for (int g = 0; g < 4; ++g)
       lo[kb][g] = aok ? a.Lo[(int64_t)al * KS + 8 * kb + 4 * h + g] : make_float2(0.f, 0.f);
-  const float2* Hrow = a.H + (int64_t)(aok ? al : 0) * tl.nsteps;
-  auto hptr = [&](int ks) { return Hrow + min(ks, tl.nsteps - 1); };
+  const float2* Hcol = a.H + (aok ? al : 0);
+  auto hptr = [&](int ks) { return Hcol + (int64_t)min(ks, tl.nsteps - 1) * a.hs; };
 
   // Hankel fragment of row block rb at K block kb: word zoff0 + 16 rb + 8 kb
   int zoff0;
@@ -1269,7 +1274,8 @@ const KernelCfg* kernel_cfgs(int* n) {
 
 // ----------------------------------------------------------------------------- small kernels
 
-// Lo[a][k] = exp(-j2pi frac(alpha_a k)), k < ks;  H[a][s] = exp(-j2pi frac(alpha_a s ks)).
+// Lo[a][k] = exp(-j2pi frac(alpha_a k)), k < ks;  H[s][a] = exp(-j2pi frac(alpha_a s ks)) (rows of
+// A cycle frequencies, so the per-step loads of a tile are coalesced).
 __global__ void tables_kernel(const double* alpha_r, int A, int ks, int nsteps, float2* Lo,
                               float2* H) {
   const int64_t per = ks + nsteps;
@@ -1283,7 +1289,7 @@ __global__ void tables_kernel(const double* alpha_r, int A, int ks, int nsteps, 
   if (k < ks)
     Lo[(int64_t)a * ks + k] = w;
   else
-    H[(int64_t)a * nsteps + (k - ks)] = w;
+    H[(int64_t)(k - ks) * A + a] = w;
 }
 
 // E[c][a] = exp(-j2pi frac(alpha_a (base0 + c Kc))) in FP64 (absolute sample index).

@@ -245,6 +245,7 @@ static hipError_t run_contract(cyc_state* s, const VSrc& v, const VSrc& vy, int6
   a.n_at = (s->A + atile - 1) / atile;
   a.n_chunks = nch;
   a.H = s->H;
+  a.hs = s->A;
   a.Lo = s->Lo;
   a.part = part ? part : s->part;
   const int64_t grid = (int64_t)a.n_tt * a.n_at * nch;
