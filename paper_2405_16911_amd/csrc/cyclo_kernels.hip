@@ -934,7 +934,7 @@ hipError_t launch_rg(const ContractArgs& a, int grid, hipStream_t st) {
 // waves, so LDS carries only the sample window, the copies and their
 // fragment reads.  Same operands and K order as contract_16_tile, so the
 // tables are bit-identical.  One barrier per K step.
-template <int PREC, int SPLIT, int RB, int NW, int KS, int IL>
+template <int PREC, int SPLIT, int RB, int NW, int KS, int IL, int PF>
 __device__ __forceinline__ void contract_16r_tile(const ContractArgs& a, TileId tid_in) {
   using O = Op<PREC>;
   constexpr int NT = 64 * NW;
@@ -953,6 +953,7 @@ __device__ __forceinline__ void contract_16r_tile(const ContractArgs& a, TileId 
   __shared__ __attribute__((aligned(16))) uint32_t Zs[2][ZS];
   __shared__ __attribute__((aligned(16))) float2 Xh[2][XW];
   __shared__ __attribute__((aligned(16))) float2 Xy[3][KS];
+  __shared__ __attribute__((aligned(16))) float2 Hs[PF == 2 ? 3 : 1][PF == 2 ? NT : 1];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int h = lane >> 5, l32 = lane & 31;
@@ -1039,7 +1040,43 @@ __device__ __forceinline__ void contract_16r_tile(const ContractArgs& a, TileId 
   // triple-buffered Xy: a wave may still read step ks's samples while
   // another writes step ks + 2's.
   static_assert(NKB % 2 == 0, "two fragment sets");
-  if (ns > 0) {
+  // the matrix-core work of step ks on Zs[zb] with the next K block's
+  // fragments generated in between (from Xy[ycur], or at the step's last
+  // block the next step's first one from Xy[ynext])
+  BFrag bf[2];
+  auto mfma_step = [&](int zb, int ycur, int ynext, float2 hcur, float2 hnext, bool more) {
+    const uint32_t* zp = &Zs[zb][0] + zoff0;
+    constexpr int NAF = 2 * (RB - 1) + NKB;
+    uint4 af[NAF];
+#pragma unroll
+    for (int o = 0; o < NAF; ++o) af[o] = *reinterpret_cast<const uint4*>(zp + 8 * o);
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+      BFrag& cur = bf[kb & 1];
+      BFrag& nxt = bf[(kb & 1) ^ 1];
+      if (kb + 1 < NKB)
+        gen_b(ycur, kb + 1, hcur, nxt);
+      else if (more)
+        gen_b(ynext, 0, hnext, nxt);
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          acc[rb][0] = O::mfma(af[2 * rb + kb], cur[b][0], acc[rb][0]);
+          acc[rb][1] = O::mfma(af[2 * rb + kb], cur[b][1], acc[rb][1]);
+        }
+    }
+    if (IL) {
+      constexpr int NMF = NKB * RB * 2 * NB;
+#pragma unroll
+      for (int i = 0; i < NMF; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, IL, 0);  // VALU
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+      }
+    }
+  };
+  if (ns > 0 && PF == 1) {
     Stager<NT, XW, KS> stg;
     stg.load(a.v, a.vy, tl.cbase, tl.tau0, tl.yend, hptr(0), tid);
     stg.store(&Xh[0][0], &Xy[0][0], tid);
@@ -1049,7 +1086,6 @@ __device__ __forceinline__ void contract_16r_tile(const ContractArgs& a, TileId 
     float2 hnext = stg.hv;
     __syncthreads();
     build_hankel(0);
-    BFrag bf[2];
     gen_b(0, 0, hcur, bf[0]);
     __syncthreads();
     int y0 = 0;  // = ks % 3
@@ -1059,36 +1095,7 @@ __device__ __forceinline__ void contract_16r_tile(const ContractArgs& a, TileId 
       const bool more = ks + 1 < ns;
       if (more)
         stg.load(a.v, a.vy, tl.cbase + (int64_t)(ks + 2) * KS, tl.tau0, tl.yend, hptr(ks + 2), tid);
-      const uint32_t* zp = &Zs[zb][0] + zoff0;
-      constexpr int NAF = 2 * (RB - 1) + NKB;
-      uint4 af[NAF];
-#pragma unroll
-      for (int o = 0; o < NAF; ++o) af[o] = *reinterpret_cast<const uint4*>(zp + 8 * o);
-#pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) {
-        BFrag& cur = bf[kb & 1];
-        BFrag& nxt = bf[(kb & 1) ^ 1];
-        if (kb + 1 < NKB)
-          gen_b(y0, kb + 1, hcur, nxt);
-        else if (more)
-          gen_b(y1, 0, hnext, nxt);
-#pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-          for (int rb = 0; rb < RB; ++rb) {
-            acc[rb][0] = O::mfma(af[2 * rb + kb], cur[b][0], acc[rb][0]);
-            acc[rb][1] = O::mfma(af[2 * rb + kb], cur[b][1], acc[rb][1]);
-          }
-      }
-      if (IL) {
-        constexpr int NMF = NKB * RB * 2 * NB;
-#pragma unroll
-        for (int i = 0; i < NMF; ++i) {
-          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
-          __builtin_amdgcn_sched_group_barrier(0x002, IL, 0);  // VALU
-          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
-        }
-      }
+      mfma_step(zb, y0, y1, hcur, hnext, more);
       if (more) {
         build_hankel(zb ^ 1);                    // step ks + 1 from Xh[zb ^ 1]
         stg.store(&Xh[zb][0], &Xy[y2][0], tid);  // step ks + 2
@@ -1099,15 +1106,54 @@ __device__ __forceinline__ void contract_16r_tile(const ContractArgs& a, TileId 
       y0 = y1;
     }
   }
+  if (ns > 0 && PF == 2) {
+    // Loads run two steps ahead in two alternating stagers; the twiddle entry
+    // of a step waits in LDS next to its samples (Hs[ks % 3][tid]), so no
+    // loaded register is carried across the unrolled loop body.
+    Stager<NT, XW, KS> sa, sb;
+    sa.load(a.v, a.vy, tl.cbase, tl.tau0, tl.yend, hptr(0), tid);
+    sa.store(&Xh[0][0], &Xy[0][0], tid);
+    Hs[0][tid] = sa.hv;
+    sb.load(a.v, a.vy, tl.cbase + KS, tl.tau0, tl.yend, hptr(1), tid);
+    sb.store(&Xh[1][0], &Xy[1][0], tid);
+    Hs[1][tid] = sb.hv;
+    sa.load(a.v, a.vy, tl.cbase + 2 * KS, tl.tau0, tl.yend, hptr(2), tid);
+    __syncthreads();
+    build_hankel(0);
+    gen_b(0, 0, Hs[0][tid], bf[0]);
+    __syncthreads();
+    int y0 = 0;  // = ks % 3
+    auto body = [&](int ks, Stager<NT, XW, KS>& cur, Stager<NT, XW, KS>& nxt) {
+      const int zb = ks & 1;
+      const int y1 = y0 == 2 ? 0 : y0 + 1, y2 = y1 == 2 ? 0 : y1 + 1;
+      const bool more = ks + 1 < ns;
+      if (more)
+        nxt.load(a.v, a.vy, tl.cbase + (int64_t)(ks + 3) * KS, tl.tau0, tl.yend, hptr(ks + 3), tid);
+      mfma_step(zb, y0, y1, Hs[y0][tid], Hs[y1][tid], more);
+      if (more) {
+        build_hankel(zb ^ 1);                    // step ks + 1 from Xh[zb ^ 1]
+        cur.store(&Xh[zb][0], &Xy[y2][0], tid);  // step ks + 2
+        Hs[y2][tid] = cur.hv;
+        __syncthreads();
+      }
+      y0 = y1;
+    };
+    int ks = 0;
+    for (; ks + 1 < ns; ks += 2) {
+      body(ks, sa, sb);
+      body(ks + 1, sb, sa);
+    }
+    if (ks < ns) body(ks, sa, sb);
+  }
   store_tiles<RB, 2, 32, 0>(a, tl.id, tl.tau0, tl.alpha0 + 32 * w, 0, 0, lane, acc);
 }
 
-template <int PREC, int SPLIT, int RB, int NW, int KS, int IL>
+template <int PREC, int SPLIT, int RB, int NW, int KS, int IL, int PF>
 __global__ __launch_bounds__(64 * NW, RB > 4 ? 1 : 2) void contract_16r(ContractArgs a) {
-  contract_16r_tile<PREC, SPLIT, RB, NW, KS, IL>(a, tile_of(a));
+  contract_16r_tile<PREC, SPLIT, RB, NW, KS, IL, PF>(a, tile_of(a));
 }
 
-template <int PREC, int SPLIT, int RB, int NW, int KS, int IL>
+template <int PREC, int SPLIT, int RB, int NW, int KS, int IL, int PF>
 __global__ __launch_bounds__(64 * NW, RB > 4 ? 1 : 2) void contract_16r_batch(BatchArgs b) {
   for (;;) {
     const int it = next_item(b.counter);
@@ -1118,19 +1164,19 @@ __global__ __launch_bounds__(64 * NW, RB > 4 ? 1 : 2) void contract_16r_batch(Ba
     id.chunk = 0;
     id.tt = bi.tt;
     id.at = bi.at;
-    contract_16r_tile<PREC, SPLIT, RB, NW, KS, IL>(job_args(b, j), id);
+    contract_16r_tile<PREC, SPLIT, RB, NW, KS, IL, PF>(job_args(b, j), id);
   }
 }
 
-template <int PREC, int SPLIT, int RB, int NW, int KS, int IL>
+template <int PREC, int SPLIT, int RB, int NW, int KS, int IL, int PF>
 hipError_t launch_16r(const ContractArgs& a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((contract_16r<PREC, SPLIT, RB, NW, KS, IL>), dim3(grid), dim3(64 * NW), 0, st, a);
+  hipLaunchKernelGGL((contract_16r<PREC, SPLIT, RB, NW, KS, IL, PF>), dim3(grid), dim3(64 * NW), 0, st, a);
   return hipGetLastError();
 }
 
-template <int PREC, int SPLIT, int RB, int NW, int KS, int IL>
+template <int PREC, int SPLIT, int RB, int NW, int KS, int IL, int PF>
 hipError_t launch_16r_batch(const BatchArgs& b, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((contract_16r_batch<PREC, SPLIT, RB, NW, KS, IL>), dim3(grid), dim3(64 * NW), 0, st, b);
+  hipLaunchKernelGGL((contract_16r_batch<PREC, SPLIT, RB, NW, KS, IL, PF>), dim3(grid), dim3(64 * NW), 0, st, b);
   return hipGetLastError();
 }
 
@@ -1175,9 +1221,9 @@ template <int TW, int AW, int WAVES_M, int WAVES_N, int KS>
 int grid_f32_batch() {
   return resident_grid(contract_f32_batch<TW, AW, WAVES_M, WAVES_N, KS>, 64 * WAVES_M * WAVES_N);
 }
-template <int PREC, int SPLIT, int RB, int NW, int KS, int IL>
+template <int PREC, int SPLIT, int RB, int NW, int KS, int IL, int PF>
 int grid_16r_batch() {
-  return resident_grid(contract_16r_batch<PREC, SPLIT, RB, NW, KS, IL>, 64 * NW);
+  return resident_grid(contract_16r_batch<PREC, SPLIT, RB, NW, KS, IL, PF>, 64 * NW);
 }
 template <int PREC, int SPLIT, int TW, int AW, int WAVES_M, int WAVES_N, int KS, int SCHED>
 int grid_16_batch() {
@@ -1218,15 +1264,15 @@ int grid_16_batch() {
   CFG_16_T(PREC_F16, "f16", 0, TW, AW, WMW, WNW, 32, 0, TBL, TN),                   \
   CFG_16_T(PREC_F16, "f16", 1, TW, AW, WMW, WNW, 32, 0, TBL, TN)
 
-#define CFG_16R(P, PN, SP, RB, NW, KS, IL)                                              \
-  {P, SP, 16 * RB, 32 * NW, KS, 64 * NW, &launch_16r<P, SP, RB, NW, KS, IL>,                \
-   PN "_s" #SP "_t" #RB "x16_a" #NW "x32_regsh_k" #KS "_i" #IL,                             \
-   &launch_16r_batch<P, SP, RB, NW, KS, IL>, &grid_16r_batch<P, SP, RB, NW, KS, IL>, 0}
-#define CFG_16R_ALL(RB, NW, KS, IL)                 \
-  CFG_16R(PREC_BF16, "bf16", 0, RB, NW, KS, IL),    \
-  CFG_16R(PREC_BF16, "bf16", 1, RB, NW, KS, IL),    \
-  CFG_16R(PREC_F16, "f16", 0, RB, NW, KS, IL),      \
-  CFG_16R(PREC_F16, "f16", 1, RB, NW, KS, IL)
+#define CFG_16R(P, PN, SP, RB, NW, KS, IL, PF)                                            \
+  {P, SP, 16 * RB, 32 * NW, KS, 64 * NW, &launch_16r<P, SP, RB, NW, KS, IL, PF>,            \
+   PN "_s" #SP "_t" #RB "x16_a" #NW "x32_regsh_k" #KS "_i" #IL "_p" #PF,                    \
+   &launch_16r_batch<P, SP, RB, NW, KS, IL, PF>, &grid_16r_batch<P, SP, RB, NW, KS, IL, PF>, 0}
+#define CFG_16R_ALL(RB, NW, KS, IL, PF)                 \
+  CFG_16R(PREC_BF16, "bf16", 0, RB, NW, KS, IL, PF),    \
+  CFG_16R(PREC_BF16, "bf16", 1, RB, NW, KS, IL, PF),    \
+  CFG_16R(PREC_F16, "f16", 0, RB, NW, KS, IL, PF),      \
+  CFG_16R(PREC_F16, "f16", 1, RB, NW, KS, IL, PF)
 
 #define CFG_RG_ALL(RB, NA, KS)                  \
   CFG_RG(PREC_BF16, "bf16", 0, RB, NA, KS),     \
@@ -1251,10 +1297,11 @@ static const KernelCfg g_cfgs[] = {
     CFG_16_ALL(128, 128, 2, 2, 32, 1),
     CFG_16_ALL(64, 64, 2, 2, 32, 0),
     CFG_RG_ALL(8, 1, 32),
-    CFG_16R_ALL(4, 4, 32, 6),
-    CFG_16R_ALL(4, 4, 32, 0),
-    CFG_16R_ALL(4, 2, 32, 0),
-    CFG_16R_ALL(8, 4, 32, 0),
+    CFG_16R_ALL(4, 4, 32, 0, 2),
+    CFG_16R_ALL(4, 4, 32, 6, 1),
+    CFG_16R_ALL(4, 4, 32, 0, 1),
+    CFG_16R_ALL(4, 2, 32, 0, 1),
+    CFG_16R_ALL(8, 4, 32, 0, 1),
     CFG_16_ALL(128, 64, 2, 2, 32, 1),
     CFG_16_ALL(128, 64, 2, 2, 32, 0),
     CFG_16_ALL(64, 64, 2, 2, 32, 8),
