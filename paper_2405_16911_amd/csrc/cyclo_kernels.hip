@@ -79,6 +79,16 @@ struct Op<PREC_BF16> {
     asm("v_cvt_pk_bf16_f32 %0, %1, -%2" : "=v"(w0) : "v"(v.x), "v"(v.y));
     asm("v_cvt_pk_bf16_f32 %0, %1, %2" : "=v"(w1) : "v"(v.y), "v"(v.x));
   }
+  static __device__ __forceinline__ uint32_t hankel0(float2 v) {
+    uint32_t w;
+    asm("v_cvt_pk_bf16_f32 %0, %1, -%2" : "=v"(w) : "v"(v.x), "v"(v.y));
+    return w;
+  }
+  static __device__ __forceinline__ uint32_t hankel1(float2 v) {
+    uint32_t w;
+    asm("v_cvt_pk_bf16_f32 %0, %1, %2" : "=v"(w) : "v"(v.y), "v"(v.x));
+    return w;
+  }
   static __device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(e8, a),
                                                   __builtin_bit_cast(e8, b), c, 0, 0, 0);
@@ -108,6 +118,8 @@ struct Op<PREC_F16> {
     w0 = pack(v.x, -v.y);
     w1 = pack(v.y, v.x);
   }
+  static __device__ __forceinline__ uint32_t hankel0(float2 v) { return pack(v.x, -v.y); }
+  static __device__ __forceinline__ uint32_t hankel1(float2 v) { return pack(v.y, v.x); }
   static __device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(e8, a),
                                                  __builtin_bit_cast(e8, b), c, 0, 0, 0);
@@ -211,6 +223,47 @@ struct Stager {
     }
   }
 };
+
+// The eight Hankel copies of one K step from the staged window Xh: unit u =
+// (sample group u / 4, shift u % 4) holds four consecutive samples in both
+// forms (re, -im) at word sh*ZP + 4 grp and (im, re) at CO + sh*ZP + 4 grp.
+// When the workgroup has two whole-wave ranges of at least ZU threads, one
+// range writes the first form and the other the second (the form is uniform
+// per wave), so no unit is done twice; otherwise every thread does whole
+// units, and units past ZU repeat earlier ones (identical values to
+// identical addresses).
+template <typename O, int NT, int ZU, int ZP, int CO>
+__device__ __forceinline__ void build_copies(const float2* Xh, uint32_t* Zs, int tid) {
+  constexpr int ZUP = (ZU + 63) / 64 * 64;
+  if constexpr (2 * ZUP <= NT) {
+    const int form = tid >= ZUP;
+    const int u = tid - form * ZUP;
+    if (u < ZU) {
+      const int grp = u >> 2, sh = u & 3;
+      uint32_t w[4];
+      if (__builtin_amdgcn_readfirstlane(form)) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k] = O::hankel1(Xh[4 * grp + sh + k]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k] = O::hankel0(Xh[4 * grp + sh + k]);
+      }
+      *reinterpret_cast<uint4*>(&Zs[form * CO + sh * ZP + 4 * grp]) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  } else {
+    constexpr int ZR = (ZU + NT - 1) / NT;
+#pragma unroll
+    for (int i = 0; i < ZR; ++i) {
+      const int u = (tid + i * NT) % ZU;
+      const int grp = u >> 2, sh = u & 3;
+      uint32_t w0[4], w1[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) O::hankel(Xh[4 * grp + sh + k], w0[k], w1[k]);
+      *reinterpret_cast<uint4*>(&Zs[sh * ZP + 4 * grp]) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
+      *reinterpret_cast<uint4*>(&Zs[CO + sh * ZP + 4 * grp]) = make_uint4(w1[0], w1[1], w1[2], w1[3]);
+    }
+  }
+}
 
 // Modulated operands of one thread: G consecutive samples of one alpha.
 // W = H * Lo, Y = conj(x) W, Yc = x W.
@@ -471,21 +524,7 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
   }
 
   auto produce = [&](int buf, float2 hv, float2 hv2) {
-    // Hankel copies from the FP32 window; unit u -> (grp = u/4, sh = u%4), units
-    // past ZU repeat earlier ones (identical values to identical addresses).
-#pragma unroll
-    for (int i = 0; i < ZR; ++i) {
-      const int u = (tid + i * NT) % ZU;
-      const int grp = u >> 2, sh = u & 3;
-      uint32_t w0[4], w1[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        O::hankel(Xh[buf][4 * grp + sh + k], w0[k], w1[k]);
-      }
-      *reinterpret_cast<uint4*>(&Zs[buf][sh * ZP + 4 * grp]) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
-      *reinterpret_cast<uint4*>(&Zs[buf][CO + sh * ZP + 4 * grp]) =
-          make_uint4(w1[0], w1[1], w1[2], w1[3]);
-    }
+    build_copies<O, NT, ZU, ZP, CO>(&Xh[buf][0], &Zs[buf][0], tid);
     // modulated operands
     uint32_t py[NB][G], pyc[NB][G];
     {
@@ -981,21 +1020,7 @@ __device__ __forceinline__ void contract_16r_tile(const ContractArgs& a, TileId 
     zoff0 = (l32 & 1) * CO + sh * ZP + (p0 - sh);
   }
 
-  auto build_hankel = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < ZR; ++i) {
-      const int u = (tid + i * NT) % ZU;
-      const int grp = u >> 2, sh = u & 3;
-      uint32_t w0[4], w1[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        O::hankel(Xh[buf][4 * grp + sh + k], w0[k], w1[k]);
-      }
-      *reinterpret_cast<uint4*>(&Zs[buf][sh * ZP + 4 * grp]) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
-      *reinterpret_cast<uint4*>(&Zs[buf][CO + sh * ZP + 4 * grp]) =
-          make_uint4(w1[0], w1[1], w1[2], w1[3]);
-    }
-  };
+  auto build_hankel = [&](int buf) { build_copies<O, NT, ZU, ZP, CO>(&Xh[buf][0], &Zs[buf][0], tid); };
 
   // modulated fragments of one K block: [b][0] table R (Y), [b][1] table Rc (Yc)
   typedef uint4 BFrag[NB][2];
