@@ -320,10 +320,25 @@ static int create_state(cyc_state** out, const double* alphas_host, int32_t n_al
   const KernelCfg& cfg = kernel_cfgs(&ncfg)[s->cfg];
   s->KS = cfg.ks;
   // Products per FP32-accumulated chunk.  A push's work is split over
-  // (alpha tiles x chunks), so a single stream keeps 4096 for every operand
-  // precision; batches take longer 16-bit chunks because their streams
-  // supply the parallelism.
-  int64_t kc = n_hops > 0 ? hop : env_i64("CYC_CHUNK", 4096);
+  // (tiles x chunks); FP32 keeps 4096.  With 16-bit operands a longer chunk
+  // halves or quarters the FP32 partials written per product (and the FP64
+  // accumulation that reads them), which pays while a push of 2^16 samples
+  // still gives at least two workgroups per CU: 16384 from 128 tiles per chunk
+  // on 256 CUs, 8192 from 64, else 4096.  (Batches take 16384: their streams
+  // supply the parallelism.)
+  int64_t kc_def = 4096;
+  if (prec != PREC_F32 && n_hops == 0) {
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+      ncu = 256;
+    const int64_t tiles = (int64_t)((s->A + cfg.aw - 1) / cfg.aw) * ((s->T + cfg.tw - 1) / cfg.tw);
+    if (tiles * 256 >= 128 * (int64_t)ncu)
+      kc_def = 16384;
+    else if (tiles * 256 >= 64 * (int64_t)ncu)
+      kc_def = 8192;
+  }
+  int64_t kc = n_hops > 0 ? hop : env_i64("CYC_CHUNK", kc_def);
   kc = std::max<int64_t>(cfg.ks, std::min<int64_t>(kc, 1 << 20));
   kc = (kc / cfg.ks) * cfg.ks;
   s->Kc = (int)kc;
