@@ -99,26 +99,26 @@ template <>
 struct Op<PREC_F16> {
   typedef _Float16 e2 __attribute__((ext_vector_type(2)));
   typedef _Float16 e8 __attribute__((ext_vector_type(8)));
-  // The empty asm makes each input an FP32 register value first, so the
-  // conversion is always FP32 -> FP16 round-to-nearest and is never fused with
-  // the FMA that produced the value (a fused form rounds once and differs in
-  // the last bit, which would make kernels disagree with each other).
+  // One packed FP32 -> FP16 round-to-nearest conversion, written out: the
+  // compiler could otherwise fuse a multiply and the conversion into a mixed
+  // FMA that rounds once, and kernels would disagree in the last bit.
   static __device__ __forceinline__ uint32_t pack(float a, float b) {
-    asm volatile("" : "+v"(a), "+v"(b));
-    e2 v;
-    v.x = (_Float16)a;
-    v.y = (_Float16)b;
-    return __builtin_bit_cast(uint32_t, v);
+    uint32_t w;
+    asm("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(w) : "v"(a), "v"(b));
+    return w;
   }
   static __device__ __forceinline__ float rnd(float a) {
-    asm volatile("" : "+v"(a));
-    return (float)(_Float16)a;
+    return (float)__builtin_bit_cast(e2, pack(a, a)).x;
   }
   static __device__ __forceinline__ void hankel(float2 v, uint32_t& w0, uint32_t& w1) {
-    w0 = pack(v.x, -v.y);
+    asm("v_cvt_pk_f16_f32 %0, %1, -%2" : "=v"(w0) : "v"(v.x), "v"(v.y));
     w1 = pack(v.y, v.x);
   }
-  static __device__ __forceinline__ uint32_t hankel0(float2 v) { return pack(v.x, -v.y); }
+  static __device__ __forceinline__ uint32_t hankel0(float2 v) {
+    uint32_t w;
+    asm("v_cvt_pk_f16_f32 %0, %1, -%2" : "=v"(w) : "v"(v.x), "v"(v.y));
+    return w;
+  }
   static __device__ __forceinline__ uint32_t hankel1(float2 v) { return pack(v.y, v.x); }
   static __device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(e8, a),
