@@ -480,7 +480,6 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
   constexpr int BP = KS + 4;                     // B row pitch (uint32), rows 16-byte aligned
   constexpr int NB = SPLIT ? 2 : 1;
   constexpr int ZU = ZW;                         // staging units: 4 entries x 1 shift x both cr
-  constexpr int ZR = (ZU + NT - 1) / NT;
 
   __shared__ __attribute__((aligned(16))) uint32_t Zs[2][ZS];
   __shared__ __attribute__((aligned(16))) uint32_t Bs[2][NB][NC][BP];
@@ -986,7 +985,6 @@ __device__ __forceinline__ void contract_16r_tile(const ContractArgs& a, TileId 
   constexpr int ZS = CO + 4 * ZP;
   constexpr int XW = ZW + 4;
   constexpr int ZU = ZW;
-  constexpr int ZR = (ZU + NT - 1) / NT;
   constexpr int NB = SPLIT ? 2 : 1;
 
   __shared__ __attribute__((aligned(16))) uint32_t Zs[2][ZS];
