@@ -55,8 +55,13 @@ extern "C" {
 /* ---- flags for cyc_create ------------------------------------------------ */
 /* Operand precision of the matrix-core contraction (accumulation is always
  * FP32 within a chunk and FP64 across chunks; the alpha*n reduction is FP64).
- * A chunk is 4096 products (the environment variable CYC_CHUNK, read at
- * creation, overrides it; batches default to 16384 for BF16/FP16). */
+ * A chunk is 4096 products with FP32 operands; with BF16/FP16 a single
+ * state takes 8192 or 16384 when a 2^16-sample push still spreads over at
+ * least two workgroups per CU (8192 from 64 lag-by-alpha tiles per chunk on
+ * 256 CUs, 16384 from 128), and batches take 16384.  The environment
+ * variable CYC_CHUNK, read at creation, overrides it.  A single state's
+ * partial-sum workspace holds eight chunks' FP32 partials, within 256 MiB ..
+ * 2 GiB (CYC_WORKSPACE_MB, read at creation, overrides it). */
 #define CYC_OP_FP32   0x0u   /* FP32 operands (default)                       */
 #define CYC_OP_BF16   0x1u   /* BF16 operands                                 */
 #define CYC_OP_FP16   0x2u   /* FP16 operands                                 */

@@ -348,7 +348,12 @@ static int create_state(cyc_state** out, const double* alphas_host, int32_t n_al
   s->PC = (int64_t)s->Kc + s->T + s->lagabs;
 
   const int64_t TA2 = 2 * (int64_t)s->T * s->A;
-  const int64_t ws_bytes = env_i64("CYC_WORKSPACE_MB", 256) << 20;
+  // Partial-sum workspace: room for eight chunks' FP32 partials (four per half
+  // of the overlapped push), within 256 MiB .. 2 GiB, so a large table still
+  // contracts a whole 2^16-sample push in one launch (at 64 lags x 65536
+  // cycle frequencies a chunk's partials are 64 MiB).
+  const int64_t ws_def_mb = std::max<int64_t>(256, std::min<int64_t>(2048, (8 * TA2 * 8 + (1 << 20) - 1) >> 20));
+  const int64_t ws_bytes = env_i64("CYC_WORKSPACE_MB", ws_def_mb) << 20;
   s->maxc = (int)std::max<int64_t>(1, std::min<int64_t>(4096, ws_bytes / (TA2 * 8)));
 
   hipStream_t st = as_stream(stream);
