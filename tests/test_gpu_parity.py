@@ -184,6 +184,34 @@ def test_every_kernel_configuration(cy):
         assert np.array_equal(ref[0], R) and np.array_equal(ref[1], Rc), info["name"]
 
 
+def test_default_chunk_length_by_shape(cy, monkeypatch):
+    """FP32 states commit 4096-product chunks; 16-bit states take 8192 or 16384
+    when a chunk has at least 64 or 128 lag-by-alpha tiles per 256 CUs (the
+    default tiles: 128 lags x 64 alphas above 64 lags, 64 x 128 at 33..64);
+    CYC_CHUNK overrides."""
+    monkeypatch.delenv("CYC_CHUNK", raising=False)
+    monkeypatch.delenv("CYC_KERNEL_CFG", raising=False)
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    bf16 = cy.CYC_OP_BF16
+
+    def chunk(T, A, flags):
+        st = cy.CyclicStream(siggen.uniform_grid(A, -0.5), T, flags)
+        info = cy.cyc_kernel_cfg_info(st.query()["kernel_cfg"])
+        k = st.query()["chunk"]
+        st.close()
+        tiles = -(-A // info["alpha_tile"]) * -(-T // info["lag_tile"])
+        return k, tiles
+
+    assert chunk(128, 4096, cy.CYC_OP_FP32)[0] == 4096
+    assert chunk(64, 65536, cy.CYC_OP_FP32)[0] == 4096
+    for T, A in [(128, 4096), (64, 65536), (32, 128), (64, 2048)]:
+        k, tiles = chunk(T, A, bf16)
+        want = 16384 if tiles * 256 >= 128 * ncu else 8192 if tiles * 256 >= 64 * ncu else 4096
+        assert k == want, (T, A, tiles, k)
+    monkeypatch.setenv("CYC_CHUNK", "4096")
+    assert chunk(64, 65536, bf16)[0] == 4096
+
+
 def test_autotune_picks_a_configuration(cy, tmp_path):
     cache = tmp_path / "tune.txt"
     os.environ["CYC_TUNE_CACHE"] = str(cache)
