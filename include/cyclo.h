@@ -55,13 +55,17 @@ extern "C" {
 /* ---- flags for cyc_create ------------------------------------------------ */
 /* Operand precision of the matrix-core contraction (accumulation is always
  * FP32 within a chunk and FP64 across chunks; the alpha*n reduction is FP64).
- * A chunk is 4096 products with FP32 operands; with BF16/FP16 a single
- * state takes 8192 or 16384 when a 2^16-sample push still spreads over at
- * least two workgroups per CU (8192 from 64 lag-by-alpha tiles per chunk on
- * 256 CUs, 16384 from 128), and batches take 16384.  The environment
- * variable CYC_CHUNK, read at creation, overrides it.  A single state's
- * partial-sum workspace holds eight chunks' FP32 partials, within 256 MiB ..
- * 2 GiB (CYC_WORKSPACE_MB, read at creation, overrides it). */
+ * A chunk is 4096 products with FP32 operands.  With BF16/FP16 a cumulative
+ * single state coalesces pushes: a push commits nothing until 2^18 products
+ * are pending (CYC_COALESCE, read at creation, sets the target; 0 commits at
+ * every push), and a read commits what is left; results are the same either
+ * way.  Its chunk is 8192 or 16384 when one such launch still spreads over at
+ * least two workgroups per CU (16384 from 32 lag-by-alpha tiles on 256 CUs,
+ * 8192 from 16; without coalescing, from 128 and 64 for a 2^16-sample push),
+ * and batches take 16384.  The environment variable CYC_CHUNK, read at
+ * creation, overrides it.  A single state's partial-sum workspace holds eight
+ * chunks' FP32 partials, within 256 MiB .. 2 GiB (CYC_WORKSPACE_MB, read at
+ * creation, overrides it). */
 #define CYC_OP_FP32   0x0u   /* FP32 operands (default)                       */
 #define CYC_OP_BF16   0x1u   /* BF16 operands                                 */
 #define CYC_OP_FP16   0x2u   /* FP16 operands                                 */
@@ -102,14 +106,17 @@ int cyc_create(cyc_state** out, const double* alphas_host, int32_t n_alpha,
 /*
  * Push a block of n complex64 samples (interleaved re, im; 8-byte aligned,
  * contiguous) that live in device memory at d_x.  Asynchronous: the caller
- * must not overwrite d_x until `stream` has passed this call.  n = 0 is a
+ * must not overwrite d_x until `stream` has passed this call (a coalescing
+ * push copies its samples into the state on `stream`).  n = 0 is a
  * no-op.  Errors: CYC_EINVAL (s NULL, n < 0, d_x NULL with n > 0),
  * CYC_ESTATE, CYC_EDEVICE (poisons the state).
  */
 int cyc_push(cyc_state* s, const void* d_x, int64_t n, void* stream);
 
 /*
- * Read the current tables without changing the state.
+ * Read the current tables without changing them: the state goes on as if the
+ * read had not happened (it may commit chunks that coalescing pushes left
+ * pending, which cyc_query then counts).
  *   d_R, d_Rc : caller-owned device buffers of T*n_alpha complex values,
  *               row-major [t][a], complex64 (or complex128 with CYC_OUT_C128);
  *               either may be NULL to skip that table.

@@ -53,6 +53,7 @@ struct cyc_state {
   bool two = false;              // two inputs (cyc_create2)
   int64_t lag_min = 0, dx = 0, dy = 0, lagabs = 0;
   int64_t PC = 0;                // pending capacity (samples)
+  int64_t G = 0;                 // a push commits nothing while fewer than G products are pending (0: at once)
   int win = 0;                   // sliding window: hops per window (0: cumulative)
   double2* ring = nullptr;       // [win][2][T][A] FP64 contribution of each hop in the window
   float2* part = nullptr;
@@ -319,13 +320,23 @@ static int create_state(cyc_state** out, const double* alphas_host, int32_t n_al
   int ncfg = 0;
   const KernelCfg& cfg = kernel_cfgs(&ncfg)[s->cfg];
   s->KS = cfg.ks;
-  // Products per FP32-accumulated chunk.  A push's work is split over
+  // Push coalescing: with 16-bit operands a 2^16-sample push is only a few
+  // hundred microseconds of contraction, so a cumulative state lets pushes
+  // pile up until 2^18 products are pending (CYC_COALESCE, read at creation;
+  // 0 commits at every push) and contracts them in one launch.  Chunks stay
+  // aligned to absolute product indices and are committed in ascending order,
+  // so results do not change; a read commits whatever is still pending.
+  const int64_t coal = (prec != PREC_F32 && n_hops == 0)
+                           ? std::max<int64_t>(0, std::min<int64_t>(env_i64("CYC_COALESCE", 1 << 18), 1 << 24))
+                           : 0;
+  // Products per FP32-accumulated chunk.  A launch's work is split over
   // (tiles x chunks); FP32 keeps 4096.  With 16-bit operands a longer chunk
   // halves or quarters the FP32 partials written per product (and the FP64
-  // accumulation that reads them), which pays while a push of 2^16 samples
-  // still gives at least two workgroups per CU: 16384 from 128 tiles per chunk
-  // on 256 CUs, 8192 from 64, else 4096.  (Batches take 16384: their streams
-  // supply the parallelism.)
+  // accumulation that reads them), which pays while one launch (the
+  // coalescing target, else a 2^16-sample push) still gives at least two
+  // workgroups per CU: 16384 from 32 lag-by-alpha tiles on 256 CUs with the
+  // 2^18 target (128 without coalescing), 8192 from 16 (64), else 4096.
+  // (Batches take 16384: their streams supply the parallelism.)
   int64_t kc_def = 4096;
   if (prec != PREC_F32 && n_hops == 0) {
     int dev = 0, ncu = 256;
@@ -333,9 +344,10 @@ static int create_state(cyc_state** out, const double* alphas_host, int32_t n_al
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
       ncu = 256;
     const int64_t tiles = (int64_t)((s->A + cfg.aw - 1) / cfg.aw) * ((s->T + cfg.tw - 1) / cfg.tw);
-    if (tiles * 256 >= 128 * (int64_t)ncu)
+    const int64_t launch = coal > 0 ? coal : 65536;
+    if (tiles * (launch / 16384) >= 2 * (int64_t)ncu)
       kc_def = 16384;
-    else if (tiles * 256 >= 64 * (int64_t)ncu)
+    else if (tiles * (launch / 8192) >= 2 * (int64_t)ncu)
       kc_def = 8192;
   }
   int64_t kc = n_hops > 0 ? hop : env_i64("CYC_CHUNK", kc_def);
@@ -344,8 +356,9 @@ static int create_state(cyc_state** out, const double* alphas_host, int32_t n_al
   s->Kc = (int)kc;
   s->nsteps = s->Kc / s->KS;
   s->win = n_hops;
-  // pending samples of either input: < Kc products plus T - 1 + |lag_min| samples
-  s->PC = (int64_t)s->Kc + s->T + s->lagabs;
+  s->G = coal > 0 ? std::max<int64_t>(kc, (coal + kc - 1) / kc * kc) : 0;
+  // pending samples of either input: < max(Kc, G) products plus T - 1 + |lag_min| samples
+  s->PC = std::max<int64_t>(s->Kc, s->G) + s->T + s->lagabs;
 
   const int64_t TA2 = 2 * (int64_t)s->T * s->A;
   // Partial-sum workspace: room for eight chunks' FP32 partials (four per half
@@ -474,16 +487,20 @@ hipError_t join_side(cyc_state* s, hipStream_t st) {
 // Push of n samples of the leading input x and the trailing input y (y == x
 // for one-input states).  Products n (absolute) pair x[n + dx + t] with
 // y[n + dy] and are committed in chunks aligned to [c Kc, (c + 1) Kc); the
-// chunk phase is referenced to y's index n + dy.
-int push_xy(cyc_state* s, const float2* x, const float2* y, int64_t n, hipStream_t st) {
+// chunk phase is referenced to y's index n + dy.  While fewer than G products
+// are pending the push only appends its samples (unless `flush`, which
+// commits every complete chunk; n may then be 0 with x = y = NULL).
+int push_xy(cyc_state* s, const float2* x, const float2* y, int64_t n, hipStream_t st, bool flush = false) {
   const int64_t L_new = s->L + n;
   const int64_t n_used_new = std::max<int64_t>(0, L_new - (s->T - 1) - s->lagabs);
-  const int64_t chunks_new = n_used_new / s->Kc - s->nc / s->Kc;
+  const bool cap = capturing(st);
+  const bool defer = !flush && !cap && s->G > 0 && n_used_new - s->nc < s->G;
+  const int64_t chunks_new = defer ? 0 : n_used_new / s->Kc - s->nc / s->Kc;
   int64_t px = 0, sx = 0, py = 0, sy = 0;
   const VSrc vx = input_src(s, s->pend, s->dx, x, n, &px, &sx);
   const VSrc vy = s->two ? input_src(s, s->pendy, s->dy, y, n, &py, &sy) : vx;
 
-  const bool overlap = s->side && chunks_new > 0 && !capturing(st);
+  const bool overlap = s->side && chunks_new > 0 && !cap;
   if (!overlap && chunks_new > 0 && join_side(s, st) != hipSuccess) return fail_device(s);
   for (int64_t done = 0; overlap && done < chunks_new;) {
     // contraction into one workspace half here, its accumulation on the side stream
@@ -582,6 +599,11 @@ int cyc_read(cyc_state* s, void* d_R, void* d_Rc, int64_t* n_used, void* stream)
         (d_Rc && launch_zero(d_Rc, tbytes, st) != hipSuccess))
       return fail_device(s);
     return CYC_OK;
+  }
+  if (nu - s->nc >= s->Kc) {
+    // complete chunks that coalescing pushes left pending
+    const int rc = push_xy(s, nullptr, nullptr, 0, st, true);
+    if (rc != CYC_OK) return rc;
   }
   if (join_side(s, st) != hipSuccess) return fail_device(s);
   const int64_t m = nu - s->nc;  // products of the pending partial chunk, < Kc
@@ -690,6 +712,7 @@ int cyc_autotune(int32_t n_alpha, int32_t n_lag, uint32_t flags, int32_t* best_c
   cyc_state* s = nullptr;
   int rc = cyc_create(&s, al.data(), n_alpha, n_lag, flags & ~CYC_OUT_C128, stream);
   if (rc != CYC_OK) return rc;
+  s->G = 0;  // every timed push commits its 16 chunks
   const int64_t nsamp = (int64_t)s->Kc * 16 + n_lag - 1;
   float2* x = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -185,12 +185,14 @@ def test_every_kernel_configuration(cy):
 
 
 def test_default_chunk_length_by_shape(cy, monkeypatch):
-    """FP32 states commit 4096-product chunks; 16-bit states take 8192 or 16384
-    when a chunk has at least 64 or 128 lag-by-alpha tiles per 256 CUs (the
-    default tiles: 128 lags x 64 alphas above 64 lags, 64 x 128 at 33..64);
-    CYC_CHUNK overrides."""
+    """FP32 states commit 4096-product chunks.  A 16-bit state takes 16384 or
+    8192 when one launch (the 2^18-product coalescing target, else a
+    2^16-sample push) still gives two workgroups per CU over its lag-by-alpha
+    tiles (the default tiles: 128 lags x 64 alphas above 64 lags, 64 x 128 at
+    33..64); CYC_CHUNK overrides."""
     monkeypatch.delenv("CYC_CHUNK", raising=False)
     monkeypatch.delenv("CYC_KERNEL_CFG", raising=False)
+    monkeypatch.delenv("CYC_COALESCE", raising=False)
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
     bf16 = cy.CYC_OP_BF16
 
@@ -202,14 +204,68 @@ def test_default_chunk_length_by_shape(cy, monkeypatch):
         tiles = -(-A // info["alpha_tile"]) * -(-T // info["lag_tile"])
         return k, tiles
 
+    def rule(tiles, launch):
+        return 16384 if tiles * (launch // 16384) >= 2 * ncu else 8192 if tiles * (launch // 8192) >= 2 * ncu else 4096
+
     assert chunk(128, 4096, cy.CYC_OP_FP32)[0] == 4096
     assert chunk(64, 65536, cy.CYC_OP_FP32)[0] == 4096
-    for T, A in [(128, 4096), (64, 65536), (32, 128), (64, 2048)]:
+    shapes = [(128, 4096), (64, 65536), (32, 128), (64, 2048), (64, 512)]
+    for T, A in shapes:
         k, tiles = chunk(T, A, bf16)
-        want = 16384 if tiles * 256 >= 128 * ncu else 8192 if tiles * 256 >= 64 * ncu else 4096
-        assert k == want, (T, A, tiles, k)
+        assert k == rule(tiles, 1 << 18), (T, A, tiles, k)
+    monkeypatch.setenv("CYC_COALESCE", "0")
+    for T, A in shapes:
+        k, tiles = chunk(T, A, bf16)
+        assert k == rule(tiles, 1 << 16), (T, A, tiles, k)
     monkeypatch.setenv("CYC_CHUNK", "4096")
     assert chunk(64, 65536, bf16)[0] == 4096
+
+
+@pytest.mark.parametrize("flags", [1, 2, 5])
+def test_push_coalescing(cy, flags, monkeypatch):
+    """16-bit pushes wait until the coalescing target is pending; the results are
+    bit for bit those of committing at every push, whatever the segmentation and
+    with reads in between, and match the oracle."""
+    x = siggen.qpsk_rrc_stream(n=40000, seed=9)
+    alphas = np.random.default_rng(11).uniform(-0.5, 0.5, size=200)
+    T = 40
+    env0 = {"CYC_CHUNK": 1024, "CYC_COALESCE": 0}
+    envc = {"CYC_CHUNK": 1024, "CYC_COALESCE": 5000}  # 5 chunks
+    ref = _run(cy, x, alphas, T, flags=flags, env=env0)
+    rng = np.random.default_rng(flags)
+    for trial in range(3):
+        cuts = np.sort(rng.choice(np.arange(1, x.size), size=5 + 15 * trial, replace=False))
+        splits = np.diff(np.concatenate([[0], cuts, [x.size]])).tolist()
+        got = _run(cy, x, alphas, T, flags=flags, splits=splits, env=envc)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), trial
+        assert got[3]["n_committed"] == ref[3]["n_committed"] == ((x.size - T + 1) // 1024) * 1024
+    # a push below the target commits nothing; one that reaches it commits every
+    # complete chunk; a read in between commits the rest and changes nothing later
+    for k, v in envc.items():
+        monkeypatch.setenv(k, str(v))
+    st = cy.CyclicStream(alphas, T, flags)
+    for k in envc:
+        monkeypatch.delenv(k)
+    xd = _dev(x)
+    st.push(xd[:4000])
+    assert st.query()["n_committed"] == 0
+    st.push(xd[4000:5150])                   # 5111 products: below 5 chunks
+    assert st.query()["n_committed"] == 0
+    st.push(xd[5150:5200])                   # 5161 products
+    assert st.query()["n_committed"] == 5 * 1024
+    st.push(xd[5200:9000])
+    assert st.query()["n_committed"] == 5 * 1024
+    R1, Rc1, n1 = st.read()
+    assert n1 == 9000 - T + 1 and st.query()["n_committed"] == 8 * 1024
+    mid = _run(cy, x[:9000], alphas, T, flags=flags, env=env0)
+    assert np.array_equal(R1.cpu().numpy(), mid[0]) and np.array_equal(Rc1.cpu().numpy(), mid[1])
+    st.push(xd[9000:])
+    R2, Rc2, n2 = st.read()
+    torch.cuda.synchronize()
+    st.close()
+    assert n2 == ref[2]
+    assert np.array_equal(R2.cpu().numpy(), ref[0]) and np.array_equal(Rc2.cpu().numpy(), ref[1])
+    _check(x, alphas, T, ref[0], ref[1], ref[2], flags, 1024, f"flags {flags}")
 
 
 def test_autotune_picks_a_configuration(cy, tmp_path):
