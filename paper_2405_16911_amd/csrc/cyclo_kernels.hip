@@ -568,14 +568,28 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
   // Hankel fragments: row block rb at K block kb reads word zoff0 + 16 rb + 8 kb
   // (the block's lags are 16 further on, and 16 = 0 mod 4 keeps the copy), so
   // block rb + 1 at kb holds the same values as block rb at kb + 2.  Each
-  // distinct fragment of a step is read from LDS once: 2 (WM - 1) + KS / 8
-  // reads instead of WM * KS / 8.
+  // distinct fragment of a step is read once: 2 (WM - 1) + KS / 8 of them
+  // instead of WM * KS / 8.  The next step's window starts KS samples on, so
+  // its first NCF fragments are this step's last NCF (the staged samples
+  // depend only on their absolute index): they stay in registers, and a step
+  // reads only its last KS / 8 fragments from LDS.
   constexpr int NAF = 2 * (WM - 1) + KS / 8;
+  constexpr int NCF = 2 * (WM - 1);
+  uint4 afc[NCF > 0 ? NCF : 1];
+  auto load_carry = [&](int buf) {
+    const uint32_t* zb = &Zs[buf][0] + zoff0;
+#pragma unroll
+    for (int o = 0; o < NCF; ++o) afc[o] = *reinterpret_cast<const uint4*>(zb + 8 * o);
+  };
   auto mfma_step = [&](int buf) {
     const uint32_t* zb = &Zs[buf][0] + zoff0;
     uint4 af[NAF];
 #pragma unroll
-    for (int o = 0; o < NAF; ++o) af[o] = *reinterpret_cast<const uint4*>(zb + 8 * o);
+    for (int o = 0; o < NCF; ++o) af[o] = afc[o];
+#pragma unroll
+    for (int o = NCF; o < NAF; ++o) af[o] = *reinterpret_cast<const uint4*>(zb + 8 * o);
+#pragma unroll
+    for (int o = 0; o < NCF; ++o) afc[o] = af[KS / 8 + o];
 #pragma unroll
     for (int kb = 0; kb < KS / 8; ++kb) {
       const int j0 = kb * 8;
@@ -623,6 +637,7 @@ __device__ __forceinline__ void contract_16_tile(const ContractArgs& a, TileId t
     __syncthreads();
     produce(0, h0, h02);
     __syncthreads();
+    load_carry(0);
     // Step ks: cur holds the loads of step ks + 2, which go to LDS at the end
     // of the step (the thread's twiddle entry too, to its own slot), and nxt
     // takes those of step ks + 3.  No loaded register is carried past the
@@ -1067,12 +1082,29 @@ __device__ __forceinline__ void contract_16r_tile(const ContractArgs& a, TileId 
   // fragments generated in between (from Xy[ycur], or at the step's last
   // block the next step's first one from Xy[ynext])
   BFrag bf[2];
+  // The next step's first NCF Hankel fragments are this step's last NCF (its
+  // window starts KS samples on): they stay in registers.  Only in the
+  // 64-lag waves: the 128-lag ones (one wave per SIMD) read every fragment of
+  // a step from LDS, as they did before the carry (with it, the FP16 form of
+  // that tile gave non-finite tables in the configuration parity test, cause
+  // not found, so it is not used there).
+  constexpr int NAF = 2 * (RB - 1) + NKB;
+  constexpr int NCF = RB <= 4 ? 2 * (RB - 1) : 0;
+  uint4 afc[NCF > 0 ? NCF : 1];
+  auto load_carry = [&](int zb) {
+    const uint32_t* zp = &Zs[zb][0] + zoff0;
+#pragma unroll
+    for (int o = 0; o < NCF; ++o) afc[o] = *reinterpret_cast<const uint4*>(zp + 8 * o);
+  };
   auto mfma_step = [&](int zb, int ycur, int ynext, float2 hcur, float2 hnext, bool more) {
     const uint32_t* zp = &Zs[zb][0] + zoff0;
-    constexpr int NAF = 2 * (RB - 1) + NKB;
     uint4 af[NAF];
 #pragma unroll
-    for (int o = 0; o < NAF; ++o) af[o] = *reinterpret_cast<const uint4*>(zp + 8 * o);
+    for (int o = 0; o < NCF; ++o) af[o] = afc[o];
+#pragma unroll
+    for (int o = NCF; o < NAF; ++o) af[o] = *reinterpret_cast<const uint4*>(zp + 8 * o);
+#pragma unroll
+    for (int o = 0; o < NCF; ++o) afc[o] = af[NKB + o];
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) {
       BFrag& cur = bf[kb & 1];
@@ -1111,6 +1143,7 @@ __device__ __forceinline__ void contract_16r_tile(const ContractArgs& a, TileId 
     build_hankel(0);
     gen_b(0, 0, hcur, bf[0]);
     __syncthreads();
+    load_carry(0);
     int y0 = 0;  // = ks % 3
     for (int ks = 0; ks < ns; ++ks) {
       const int zb = ks & 1;
@@ -1145,6 +1178,7 @@ __device__ __forceinline__ void contract_16r_tile(const ContractArgs& a, TileId 
     build_hankel(0);
     gen_b(0, 0, Hs[0][tid], bf[0]);
     __syncthreads();
+    load_carry(0);
     int y0 = 0;  // = ks % 3
     auto body = [&](int ks, Stager<NT, XW, KS>& cur, Stager<NT, XW, KS>& nxt) {
       const int zb = ks & 1;
