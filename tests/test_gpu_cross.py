@@ -152,3 +152,31 @@ def test_cross_edge_cases(cy):
         cy._check(cy.lib().cyc_push2(st._s, cy.ctypes.c_void_p(d.data_ptr()), cy.ctypes.c_void_p(d.data_ptr()),
                                      10, None), "cyc_push2")
     st.close()
+
+
+@pytest.mark.parametrize("flags", [1, 2])
+def test_cross_push_coalescing_bitwise(cy, flags, monkeypatch):
+    """Two inputs with lags of either sign: pushes that coalesce until five
+    1024-product chunks are pending (both inputs' pending buffers then hold
+    more than a chunk) give the bits of committing at every push, and match
+    the oracle."""
+    lag_min, T = -19, 40
+    L = 30000
+    x, y = _signals(L, 14)
+    alphas = np.linspace(-0.5, 0.5, 150, endpoint=False)
+    monkeypatch.setenv("CYC_CHUNK", "1024")
+    monkeypatch.setenv("CYC_COALESCE", "0")
+    ref = _run(cy, x, y, alphas, lag_min, T, flags)
+    monkeypatch.setenv("CYC_COALESCE", "5000")
+    rng = np.random.default_rng(20 + flags)
+    for trial in range(2):
+        cuts = list(rng.integers(1, L, size=6 + 10 * trial)) + [4000, 5200, 9000]
+        got = _run(cy, x, y, alphas, lag_min, T, flags, splits=cuts)
+        assert got[2] == ref[2] and np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), trial
+    Ro, Rco, no = cross_tables(x, y, alphas, lag_min, T)
+    assert ref[2] == no
+    sc = _scale(x, y, lag_min, T)[:, None]
+    r = _rratio(x, y, lag_min, T)[:, None]
+    ratio = max(np.max(np.abs(ref[0] - Ro) / sc / bound(flags, 1024, r, np.abs(Ro) / sc)),
+                np.max(np.abs(ref[1] - Rco) / sc / bound(flags, 1024, r, np.abs(Rco) / sc)))
+    assert ratio <= 1.0
